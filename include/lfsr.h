@@ -1,0 +1,184 @@
+/*
+ * lfsr.h -- C ABI of the MI355X (gfx950) light-field super-resolution solver.
+ *
+ * The solver minimises, over the high-resolution (HR) reference view x,
+ *
+ *   J(x) = lambda1 sum_k |A_k x - y_k|_1 + lambda2 sum_k |A_k x - y_k|_2^2
+ *          + sum_d | V_d (x - S_d x) |_1                                   (paper sec 4, cost J)
+ *
+ * with the per-view forward model A_k = D B W_k (sec 3.1): a disparity warp
+ * W_k of x to angular view k, a Gaussian blur B and a decimation D that keeps
+ * the top-left pixel of every scale x scale block (sec 4.1).  The regulariser
+ * is weighted non-local TV over the offsets d of an NLTV window with weights
+ * V_d(z) = exp(-|d|^2/sigma_s) * exp(-|grad x(z)|^2/sigma_e) * occ(z)
+ * (sec 3.4).  The minimiser is the ADMM iteration of sec 5, Algorithm 1 (z-
+ * and w-steps before the x-step, the penalty absorbed into the dual) with the
+ * x-step solved by the conjugate-gradient loop of Algorithm 2.
+ *
+ * Layouts (all row-major, no padding, float32 unless stated):
+ *   LR views   y     [s_k][lr_h][lr_w], s_k = ang_rows*ang_cols, view k at
+ *                    angular row k / ang_cols and column k % ang_cols; the
+ *                    reference is the centre view.
+ *   disparity  disp  [H][W], H = scale*lr_h, W = scale*lr_w: HR pixels of
+ *                    shift per unit angular step, defined on the reference
+ *                    view.  View k (angular offset tau_k rows, rho_k columns
+ *                    from the centre) samples x bilinearly at
+ *                    (Y + tau_k*disp(Y,X), X + rho_k*disp(Y,X)); samples
+ *                    outside the image read zero (sec 4.1).
+ *   HR image   x     [H][W].
+ *   data dual  w_D   [s_k][lr_h][lr_w]; NLTV dual w_S [s_d][H][W] with the
+ *                    s_d = nltv_window^2 - 1 offsets d = (dy,dx) row-major
+ *                    over the window, centre skipped.
+ *
+ * Ownership: every pointer is owned by the caller.  Pointers named d_* are
+ * device (HBM) pointers, h_* host pointers.  The library allocates no device
+ * memory: the caller provides one workspace of lfsr_workspace_bytes() bytes
+ * (256-byte aligned) that must outlive the handle.  Input buffers bound by
+ * lfsr_init() must stay alive and unchanged until the last lfsr_iterate().
+ *
+ * Streams: every call that takes a hip_stream (a hipStream_t; NULL = the
+ * default stream) only enqueues work on it and returns, unless documented as
+ * synchronising.  One handle must not be used from two streams at once.
+ *
+ * Errors: return codes only; no exception crosses this interface.  Parameter
+ * errors are caught by lfsr_create() (LFSR_EINVAL).  Input-data errors found
+ * on the device (non-finite values, disparity beyond disp_bound) are recorded
+ * on the device and reported by the next synchronising call
+ * (lfsr_get_stats, or lfsr_solve with h_stats != NULL).  A failed HIP call
+ * makes the handle unusable (LFSR_EDEVICE now, LFSR_ESTATE afterwards).
+ * lfsr_last_error() returns a description of the last failure.
+ */
+#ifndef LFSR_H
+#define LFSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lfsr_handle lfsr_handle;
+
+typedef enum {
+  LFSR_OK = 0,
+  LFSR_EINVAL = -1,     /* bad parameter, size, pointer or input data */
+  LFSR_ENOMEM = -2,     /* workspace missing or too small */
+  LFSR_EDEVICE = -3,    /* a HIP runtime call failed */
+  LFSR_ESTATE = -4,     /* call out of order, or handle broken by an earlier device error */
+  LFSR_ENONFINITE = -5, /* NaN/Inf in the inputs */
+  LFSR_EBUSY = -6       /* reserved */
+} lfsr_status;
+
+typedef enum { LFSR_F32 = 0, LFSR_F16 = 1, LFSR_BF16 = 2 } lfsr_storage;
+
+typedef struct {
+  int32_t ang_rows, ang_cols; /* U, V: angular grid, both odd (centre view = reference) */
+  int32_t lr_h, lr_w;         /* s_y, s_x: LR view size */
+  int32_t scale;              /* zeta >= 1: HR = scale * LR (sec 4.1) */
+  int32_t n_disp;             /* 1: one disparity map on the reference view (the only form supported) */
+  int32_t blur_size;          /* odd, 1..31; <= 0 with blur_sigma <= 0: paper default (see below) */
+  float blur_sigma;           /* Gaussian std-dev in HR px; <= 0: sqrt(scale^2-1)/4 (sec 4.1), size 2*ceil(3 sigma)+1 */
+  float lambda1, lambda2;     /* l1 and l2 fidelity weights (sec 3.3), >= 0, not both 0 */
+  int32_t nltv_window;        /* odd, 1..15; 1 switches the regulariser off */
+  float sigma_s;              /* spatial weight scale (sec 3.4), > 0 */
+  float sigma_e;              /* edge weight scale (sec 3.4), > 0; +INF: no edge weight */
+  int32_t reweight;           /* 1: edge weight recomputed from x at every ADMM iteration (sec 7.1); 0: from x0 only */
+  float admm_penalty;         /* vartheta > 0 (sec 4) */
+  int32_t admm_iters;         /* N >= 1 (Algorithm 1) */
+  int32_t cg_iters;           /* K >= 0 (Algorithm 2) */
+  float cg_tol;               /* tau >= 0: CG continues while |r|^2 > tau (0: exactly K steps unless r = 0) */
+  float stop_tol;             /* >= 0: stop after iteration n once res_n <= stop_tol * res_1 (0: run N) */
+  float disp_bound;           /* > 0: the caller's bound on |disp| (sizes the warp halo; larger values are an input error) */
+  int32_t storage;            /* lfsr_storage of the dual fields and LR work buffers (LFSR_F32 only in this version) */
+} lfsr_params;
+
+#define LFSR_NSTAT 6
+typedef struct {
+  int32_t iters_run;    /* ADMM iterations completed since lfsr_init */
+  int32_t cg_steps;     /* CG steps taken in the last iteration */
+  double objective;     /* J(x^(n-1)) of the last iteration n (FP64 reduction) */
+  double primal_res;    /* |w^(n) - w^(n-1)|_2 over both dual blocks */
+  double cg_pi;         /* final |r|^2 of the last x-step */
+  double* h_hist;       /* NULL, or caller memory for [admm_iters][LFSR_NSTAT] doubles:
+                           {J, primal residual, final pi, CG steps, data part, regulariser part} */
+} lfsr_stats;
+
+/* Bytes of device workspace a handle with these parameters needs; 0 if the
+ * parameters are invalid (lfsr_last_error(NULL) says why). Host-only. */
+size_t lfsr_workspace_bytes(const lfsr_params* p);
+
+/* Validate p and build a handle over the caller's workspace (d_workspace, at
+ * least lfsr_workspace_bytes(p) bytes, 256-byte aligned).  Host-only: touches
+ * no device memory. */
+lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, lfsr_handle** out);
+
+/* Release the handle (NULL-safe).  Does not free the workspace. */
+void lfsr_destroy(lfsr_handle* h);
+
+/* Text of the last error on h, or of the calling thread's last handle-less
+ * error when h is NULL.  Never NULL. */
+const char* lfsr_last_error(const lfsr_handle* h);
+
+/* Complete solve (Algorithm 1): lfsr_init + lfsr_iterate(admm_iters) + copy
+ * of x into d_hr_out [H][W].  Asynchronous on hip_stream unless h_stats is
+ * non-NULL, in which case it synchronises and fills *h_stats. */
+lfsr_status lfsr_solve(lfsr_handle* h, const float* d_lr, const float* d_disp, const float* d_occ,
+                       const float* d_x0, float* d_hr_out, lfsr_stats* h_stats, void* hip_stream);
+
+/* Bind the inputs (d_lr [s_k][lr_h][lr_w], d_disp [H][W], d_occ [H][W]
+ * occlusion weight or NULL = 1) and set the state to x = d_x0 (or, if NULL,
+ * the bicubic up-sampling of the centre view: Keys a = -1/2, LR sample (i,j)
+ * at HR (scale*i, scale*j), clamp-to-edge; sec 5), w_D = w_S = 0, n = 0.
+ * Enqueues an input check (non-finite values; |disp| > disp_bound). */
+lfsr_status lfsr_init(lfsr_handle* h, const float* d_lr, const float* d_disp, const float* d_occ,
+                      const float* d_x0, void* hip_stream);
+
+/* Run `count` more ADMM iterations (sec 5, Algorithm 1) on the bound inputs. */
+lfsr_status lfsr_iterate(lfsr_handle* h, int32_t count, void* hip_stream);
+
+/* Copy the state out as float32: x [H][W], w_D [s_k][lr_h][lr_w],
+ * w_S [s_d][H][W], the weight map m = w_e * occ [H][W].  Any pointer may be NULL. */
+lfsr_status lfsr_read_state(lfsr_handle* h, float* d_x, float* d_wd, float* d_ws, float* d_m,
+                            void* hip_stream);
+
+/* Replace the state (checkpoint resume): same layouts as lfsr_read_state;
+ * n_done = iterations already run (decides whether the edge weight is
+ * recomputed on the next iteration when reweight = 0).  All pointers
+ * required except d_m when reweight = 1. */
+lfsr_status lfsr_write_state(lfsr_handle* h, const float* d_x, const float* d_wd, const float* d_ws,
+                             const float* d_m, int32_t n_done, void* hip_stream);
+
+/* Synchronise hip_stream and report statistics (see lfsr_stats).  Returns
+ * LFSR_ENONFINITE / LFSR_EINVAL if the input check of lfsr_init failed. */
+lfsr_status lfsr_get_stats(lfsr_handle* h, lfsr_stats* out, void* hip_stream);
+
+/* Operators of the forward model on the handle's geometry (sec 3.1, 4.1):
+ *   lfsr_forward: d_lr_out[k] = A_k d_x = D B W_k d_x for every view k.
+ *   lfsr_adjoint: d_hr_out = sum_k A_k^T d_lr[k] (exact transpose; W_k^T is
+ *                 the scatter with the bilinear weights of W_k).
+ *   lfsr_normal:  d_out = (lambda2 + vartheta*lambda1^2/2) A^T A d_p
+ *                         + (vartheta/2) S^T S d_p with the weights of d_m
+ *                 (the x-step normal operator G^T G of sec 5).
+ * They use the handle's work buffers, so they must not overlap an iteration. */
+lfsr_status lfsr_forward(lfsr_handle* h, const float* d_x, const float* d_disp, float* d_lr_out,
+                         void* hip_stream);
+lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp, float* d_hr_out,
+                         void* hip_stream);
+lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, const float* d_m,
+                        float* d_out, void* hip_stream);
+
+/* sec 3.4: d_m_out = exp(-|grad x|^2 / sigma_e) * occ (forward differences,
+ * zero at the last row/column; occ NULL = 1). */
+lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_occ, float* d_m_out,
+                             void* hip_stream);
+
+/* sec 5: bicubic up-sampling of one LR view d_lr_view [lr_h][lr_w] to [H][W]
+ * (the x0 of lfsr_init). */
+lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LFSR_H */

@@ -1,0 +1,503 @@
+// C ABI of the light-field super-resolution solver (include/lfsr.h): parameter
+// validation, tiling plan, workspace layout and the per-iteration launch
+// schedule of the ADMM loop (arXiv 2206.05047, sec 5, Algorithms 1 and 2).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lfsr.h"
+#include "lfsr_internal.h"
+
+using namespace lfsr;
+
+namespace {
+
+thread_local std::string g_thread_err = "no error";
+
+struct Plan {
+  Geom g;
+  size_t off_x, off_m, off_vs, off_r, off_pv, off_hp, off_wd, off_ws0, off_ws1, off_lr, off_adj, off_part,
+      off_stats, off_sc;
+  size_t bytes;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+bool fail(std::string* err, const char* msg) {
+  if (err) *err = msg;
+  return false;
+}
+
+// Tiling for the forward and adjoint kernels; false if the warp halo is too
+// large for any LDS tile.
+bool choose_tiles(Geom& g, std::string* err) {
+  // forward: LR tile, largest of 16x16 / 16x8 / 8x8 / 8x4 / 4x4 whose LDS fits
+  const int fcand[5][2] = {{16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 4}};
+  bool ok = false;
+  for (auto& c : fcand) {
+    g.f_tly = c[0];
+    g.f_tlx = c[1];
+    if (forward_lds(g) <= 60 * 1024) {
+      ok = true;
+      break;
+    }
+  }
+  if (!ok) return fail(err, "disp_bound too large: the forward warp halo does not fit in LDS");
+  const long long ftiles = (long long)((g.sy + g.f_tly - 1) / g.f_tly) * ((g.sx + g.f_tlx - 1) / g.f_tlx);
+  long long vpb = (ftiles * g.sk + 3071) / 3072;
+  if (vpb < 1) vpb = 1;
+  if (vpb > g.sk) vpb = g.sk;
+  g.f_vpb = (int)vpb;
+
+  // adjoint: prefer >= 1024 tiles; HR tile must be at least the halo and
+  // hold <= kAdjMaxPix pixels per thread
+  const int acand[5][2] = {{16, 8}, {8, 8}, {8, 4}, {4, 4}, {4, 2}};
+  int best = -1;
+  for (int ci = 0; ci < 5; ++ci) {
+    Geom t = g;
+    t.a_tly = acand[ci][0];
+    t.a_tlx = acand[ci][1];
+    t.a_th = t.a_tly * g.zeta;
+    t.a_tw = t.a_tlx * g.zeta;
+    t.a_ey = t.a_th + 2 * g.halo;
+    t.a_ex = t.a_tw + 2 * g.halo;
+    if (t.a_th < g.halo || t.a_tw < g.halo) continue;
+    if ((long long)t.a_th * t.a_tw > (long long)kThreads * kAdjMaxPix) continue;
+    if (adjoint_lds(t) > 60 * 1024) continue;
+    const long long nt = (long long)((g.sy + t.a_tly - 1) / t.a_tly) * ((g.sx + t.a_tlx - 1) / t.a_tlx);
+    best = ci;
+    if (nt >= 1024) break;
+  }
+  if (best < 0) return fail(err, "disp_bound too large for the adjoint tiling (halo exceeds tile or LDS)");
+  g.a_tly = acand[best][0];
+  g.a_tlx = acand[best][1];
+  g.a_th = g.a_tly * g.zeta;
+  g.a_tw = g.a_tlx * g.zeta;
+  g.a_ey = g.a_th + 2 * g.halo;
+  g.a_ex = g.a_tw + 2 * g.halo;
+  g.a_nty = (g.sy + g.a_tly - 1) / g.a_tly;
+  g.a_ntx = (g.sx + g.a_tlx - 1) / g.a_tlx;
+  g.a_npix = (g.a_th * g.a_tw + kThreads - 1) / kThreads;
+  return true;
+}
+
+bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
+  if (!p) return fail(err, "params is NULL");
+  std::memset(pl, 0, sizeof(*pl));
+  Geom& g = pl->g;
+  if (p->ang_rows < 1 || p->ang_cols < 1 || p->ang_rows > 63 || p->ang_cols > 63)
+    return fail(err, "ang_rows/ang_cols must be in 1..63");
+  if (p->ang_rows % 2 == 0 || p->ang_cols % 2 == 0) return fail(err, "ang_rows/ang_cols must be odd (centre view)");
+  if (p->lr_h < 1 || p->lr_w < 1) return fail(err, "lr_h/lr_w must be >= 1");
+  if (p->scale < 1 || p->scale > 8) return fail(err, "scale must be in 1..8");
+  if ((long long)p->lr_h * p->scale > 32768 || (long long)p->lr_w * p->scale > 32768)
+    return fail(err, "HR size above 32768 per side");
+  if (p->n_disp != 1) return fail(err, "n_disp must be 1 (one disparity map on the reference view)");
+  if (!(std::isfinite(p->lambda1) && std::isfinite(p->lambda2)) || p->lambda1 < 0.f || p->lambda2 < 0.f ||
+      p->lambda1 + p->lambda2 <= 0.f)
+    return fail(err, "lambda1, lambda2 must be finite, >= 0 and not both 0");
+  if (p->nltv_window < 1 || p->nltv_window > kMaxWin || p->nltv_window % 2 == 0)
+    return fail(err, "nltv_window must be odd in 1..15");
+  if (!(p->sigma_s > 0.f) || !std::isfinite(p->sigma_s)) return fail(err, "sigma_s must be finite and > 0");
+  if (!(p->sigma_e > 0.f)) return fail(err, "sigma_e must be > 0 (+INF disables the edge weight)");
+  if (!(p->admm_penalty > 0.f) || !std::isfinite(p->admm_penalty)) return fail(err, "admm_penalty must be > 0");
+  if (p->admm_iters < 1 || p->admm_iters > 1000000) return fail(err, "admm_iters must be in 1..1e6");
+  if (p->cg_iters < 0 || p->cg_iters > 100000) return fail(err, "cg_iters must be in 0..1e5");
+  if (!(p->cg_tol >= 0.f) || !std::isfinite(p->cg_tol)) return fail(err, "cg_tol must be finite and >= 0");
+  if (!(p->stop_tol >= 0.f) || !std::isfinite(p->stop_tol)) return fail(err, "stop_tol must be finite and >= 0");
+  if (!(p->disp_bound > 0.f) || !std::isfinite(p->disp_bound) || p->disp_bound > 256.f)
+    return fail(err, "disp_bound must be in (0, 256]");
+  if (p->reweight != 0 && p->reweight != 1) return fail(err, "reweight must be 0 or 1");
+  if (p->storage != LFSR_F32) return fail(err, "only LFSR_F32 storage is supported in this version");
+
+  g.U = p->ang_rows;
+  g.V = p->ang_cols;
+  g.sk = g.U * g.V;
+  g.kref = (g.U / 2) * g.V + g.V / 2;
+  g.sy = p->lr_h;
+  g.sx = p->lr_w;
+  g.zeta = p->scale;
+  g.H = g.zeta * g.sy;
+  g.W = g.zeta * g.sx;
+  g.q = (long long)g.sy * g.sx;
+  g.p = (long long)g.H * g.W;
+
+  // blur (sec 4.1): normalised Gaussian; sigma <= 0 -> sqrt(zeta^2-1)/4
+  double sigma = p->blur_sigma;
+  int kb = p->blur_size;
+  if (!(sigma > 0.0)) {
+    sigma = std::sqrt((double)g.zeta * g.zeta - 1.0) / 4.0;
+    if (kb <= 0) kb = sigma > 0.0 ? 2 * (int)std::ceil(3.0 * sigma) + 1 : 1;
+  } else if (kb <= 0) {
+    kb = 2 * (int)std::ceil(3.0 * sigma) + 1;
+  }
+  if (!std::isfinite(sigma)) return fail(err, "blur_sigma must be finite");
+  if (kb < 1 || kb > kMaxTaps || kb % 2 == 0) return fail(err, "blur_size must be odd in 1..31");
+  g.kb = kb;
+  g.rb = kb / 2;
+  {
+    double s = 0.0, t[kMaxTaps];
+    for (int a = 0; a < kb; ++a) {
+      const double d = a - g.rb;
+      t[a] = sigma > 0.0 ? std::exp(-d * d / (2.0 * sigma * sigma)) : (d == 0.0 ? 1.0 : 0.0);
+      s += t[a];
+    }
+    for (int a = 0; a < kb; ++a) g.g[a] = (float)(t[a] / s);
+  }
+
+  // NLTV (sec 3.4, 4.1): offsets row-major over the window, centre skipped
+  g.win = p->nltv_window;
+  g.rw = g.win / 2;
+  g.sd = g.win * g.win - 1;
+  {
+    const int half = (g.win * g.win) / 2;
+    for (int d = 0; d < g.sd; ++d) {
+      const int id = d < half ? d : d + 1;
+      const int dy = id / g.win - g.rw, dx = id % g.win - g.rw;
+      const double c = std::exp(-(double)(dy * dy + dx * dx) / (double)p->sigma_s);
+      g.cd[d] = (float)c;
+      g.cd2[d] = (float)(c * c);
+    }
+  }
+  g.lambda1 = p->lambda1;
+  g.lambda2 = p->lambda2;
+  g.half_theta = 0.5f * p->admm_penalty;
+  g.clip = (float)(1.0 / (double)p->admm_penalty);
+  g.cA = (float)((double)p->lambda2 + 0.5 * (double)p->admm_penalty * (double)p->lambda1 * p->lambda1);
+  g.use_edge = std::isfinite(p->sigma_e) ? 1 : 0;
+  g.inv_sigma_e = g.use_edge ? (float)(1.0 / (double)p->sigma_e) : 0.f;
+  g.disp_bound = p->disp_bound;
+  g.cg_tol = p->cg_tol;
+  g.stop_tol = p->stop_tol;
+  {
+    const int tmax = (g.U - 1) / 2 > (g.V - 1) / 2 ? (g.U - 1) / 2 : (g.V - 1) / 2;
+    g.halo = (int)std::ceil((double)tmax * (double)p->disp_bound) + 1;
+  }
+  if (!choose_tiles(g, err)) return false;
+
+  // workspace layout
+  const size_t P = (size_t)g.p, Q = (size_t)g.q;
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    size_t at = o;
+    o = align256(o + n);
+    return at;
+  };
+  pl->off_sc = take(sizeof(DevScalars));
+  pl->off_x = take(P * 4);
+  pl->off_m = take(P * 4);
+  pl->off_vs = take(P * 4);
+  pl->off_r = take(P * 4);
+  pl->off_pv = take(P * 4);
+  pl->off_hp = take(P * 4);
+  pl->off_wd = take((size_t)g.sk * Q * 4);
+  pl->off_ws0 = take((size_t)g.sd * P * 4);
+  pl->off_ws1 = take((size_t)g.sd * P * 4);
+  pl->off_lr = take((size_t)g.sk * Q * 4);
+  pl->off_adj = take((size_t)g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4);
+  {
+    const dim3 fg = forward_grid(g), tg = tv_grid(g);
+    size_t nb = (size_t)fg.x * fg.y * fg.z * 3;
+    nb = std::max(nb, (size_t)tg.x * tg.y * 2);
+    nb = std::max(nb, (size_t)kRedBlocks);
+    pl->off_part = take(nb * sizeof(double));
+  }
+  pl->off_stats = take((size_t)p->admm_iters * LFSR_NSTAT * sizeof(double));
+  pl->bytes = o;
+  return true;
+}
+
+}  // namespace
+
+struct lfsr_handle {
+  lfsr_params prm;
+  Plan plan;
+  Bufs b;
+  char* ws;
+  int n_done;
+  bool bound;
+  bool broken;
+  const float* y;
+  const float* disp;
+  const float* occ;
+  std::string err;
+};
+
+namespace {
+
+lfsr_status set_err(lfsr_handle* h, lfsr_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_thread_err = msg;
+  return st;
+}
+
+// Check for launch errors after enqueueing work.
+lfsr_status check_hip(lfsr_handle* h, const char* where) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    h->broken = true;
+    return set_err(h, LFSR_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+  }
+  return LFSR_OK;
+}
+
+lfsr_status usable(lfsr_handle* h) {
+  if (!h) return set_err(nullptr, LFSR_EINVAL, "handle is NULL");
+  if (h->broken) return set_err(h, LFSR_ESTATE, "handle unusable after an earlier device error: " + h->err);
+  return LFSR_OK;
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// One ADMM iteration (Algorithm 1 with the CG x-step of Algorithm 2).
+void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
+  const Geom& g = h->plan.g;
+  const Bufs& b = h->b;
+  const int n = h->n_done + 1;
+  const int row = std::min(n, h->prm.admm_iters) - 1;
+  double* stats_row = b.stats + (size_t)row * LFSR_NSTAT;
+  // weights from x^(n-1) (sec 7.1: recomputed every iteration when reweighting)
+  if (h->prm.reweight || n == 1) launch_edge(g, b.x, h->occ, b.m, s, b, 1);
+  // z/w-steps of both blocks; e and the NLTV divergence feed v
+  launch_forward_wzd(g, b.x, h->disp, h->y, s, b);
+  if (g.sd > 0) launch_tv(g, s, b);
+  launch_adjoint(g, b.lr, h->disp, s, b, 1);
+  launch_cginit(g, stats_row, s, b);
+  // x-step: K CG steps on G^T G delta = -v, accumulated straight into x
+  for (int k = 0; k < h->prm.cg_iters; ++k) {
+    launch_forward(g, b.pv, h->disp, b.lr, s, b, 3);
+    launch_adjoint(g, b.lr, h->disp, s, b, 3);
+    launch_hp(g, b.pv, b.m, b.hp, s, b, 3, 1);
+    launch_cgupd(g, s, b);
+    launch_cgp(g, s, b);
+  }
+  launch_iter_end(g, stats_row, s, b);
+  h->n_done = n;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lfsr_workspace_bytes(const lfsr_params* p) {
+  Plan pl;
+  std::string err;
+  if (!make_plan(p, &pl, &err)) {
+    g_thread_err = err;
+    return 0;
+  }
+  return pl.bytes;
+}
+
+lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, lfsr_handle** out) {
+  if (!out) return set_err(nullptr, LFSR_EINVAL, "out is NULL");
+  *out = nullptr;
+  Plan pl;
+  std::string err;
+  if (!make_plan(p, &pl, &err)) return set_err(nullptr, LFSR_EINVAL, err);
+  if (!d_workspace) return set_err(nullptr, LFSR_ENOMEM, "workspace is NULL");
+  if (((uintptr_t)d_workspace & 255) != 0) return set_err(nullptr, LFSR_EINVAL, "workspace not 256-byte aligned");
+  if (bytes < pl.bytes)
+    return set_err(nullptr, LFSR_ENOMEM,
+                   "workspace too small: need " + std::to_string(pl.bytes) + " bytes, got " + std::to_string(bytes));
+  lfsr_handle* h = new (std::nothrow) lfsr_handle();
+  if (!h) return set_err(nullptr, LFSR_ENOMEM, "host allocation of the handle failed");
+  h->prm = *p;
+  h->plan = pl;
+  h->ws = (char*)d_workspace;
+  char* w = h->ws;
+  h->b.sc = (DevScalars*)(w + pl.off_sc);
+  h->b.x = (float*)(w + pl.off_x);
+  h->b.m = (float*)(w + pl.off_m);
+  h->b.vs = (float*)(w + pl.off_vs);
+  h->b.r = (float*)(w + pl.off_r);
+  h->b.pv = (float*)(w + pl.off_pv);
+  h->b.hp = (float*)(w + pl.off_hp);
+  h->b.wD = (float*)(w + pl.off_wd);
+  h->b.wS[0] = (float*)(w + pl.off_ws0);
+  h->b.wS[1] = (float*)(w + pl.off_ws1);
+  h->b.lr = (float*)(w + pl.off_lr);
+  h->b.adj = (float*)(w + pl.off_adj);
+  h->b.part = (double*)(w + pl.off_part);
+  h->b.stats = (double*)(w + pl.off_stats);
+  h->n_done = 0;
+  h->bound = false;
+  h->broken = false;
+  h->err = "no error";
+  *out = h;
+  return LFSR_OK;
+}
+
+void lfsr_destroy(lfsr_handle* h) { delete h; }
+
+const char* lfsr_last_error(const lfsr_handle* h) { return h ? h->err.c_str() : g_thread_err.c_str(); }
+
+lfsr_status lfsr_init(lfsr_handle* h, const float* d_lr, const float* d_disp, const float* d_occ,
+                      const float* d_x0, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_lr || !d_disp) return set_err(h, LFSR_EINVAL, "d_lr and d_disp are required");
+  const Geom& g = h->plan.g;
+  hipStream_t s = S(hip_stream);
+  h->y = d_lr;
+  h->disp = d_disp;
+  h->occ = d_occ;
+  launch_reset(0, s, h->b);
+  launch_check(g, d_lr, d_disp, d_occ, s, h->b);
+  launch_fill(h->b.wD, (long long)g.sk * g.q, 0.f, s);
+  launch_fill(h->b.wS[0], (long long)g.sd * g.p, 0.f, s);
+  launch_fill(h->b.m, g.p, 1.f, s);
+  if (d_x0) {
+    if (hipMemcpyAsync(h->b.x, d_x0, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return check_hip(h, "lfsr_init copy x0");
+  } else {
+    launch_bicubic(g, d_lr + (size_t)g.kref * g.q, h->b.x, s);
+  }
+  h->n_done = 0;
+  h->bound = true;
+  return check_hip(h, "lfsr_init");
+}
+
+lfsr_status lfsr_iterate(lfsr_handle* h, int32_t count, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!h->bound) return set_err(h, LFSR_ESTATE, "lfsr_iterate before lfsr_init / lfsr_write_state");
+  if (count < 0) return set_err(h, LFSR_EINVAL, "count must be >= 0");
+  hipStream_t s = S(hip_stream);
+  for (int i = 0; i < count; ++i) enqueue_iteration(h, s);
+  return check_hip(h, "lfsr_iterate");
+}
+
+lfsr_status lfsr_read_state(lfsr_handle* h, float* d_x, float* d_wd, float* d_ws, float* d_m, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  const Geom& g = h->plan.g;
+  hipStream_t s = S(hip_stream);
+  if (d_x && hipMemcpyAsync(d_x, h->b.x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return check_hip(h, "lfsr_read_state x");
+  if (d_wd && hipMemcpyAsync(d_wd, h->b.wD, (size_t)g.sk * g.q * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return check_hip(h, "lfsr_read_state w_D");
+  if (d_ws) launch_copy_ws(d_ws, (long long)g.sd * g.p, s, h->b);
+  if (d_m && hipMemcpyAsync(d_m, h->b.m, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return check_hip(h, "lfsr_read_state m");
+  return check_hip(h, "lfsr_read_state");
+}
+
+lfsr_status lfsr_write_state(lfsr_handle* h, const float* d_x, const float* d_wd, const float* d_ws,
+                             const float* d_m, int32_t n_done, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  const Geom& g = h->plan.g;
+  if (!d_x || !d_wd || (g.sd > 0 && !d_ws)) return set_err(h, LFSR_EINVAL, "d_x, d_wd and d_ws are required");
+  if (!h->prm.reweight && n_done > 0 && !d_m) return set_err(h, LFSR_EINVAL, "d_m required when reweight = 0");
+  if (n_done < 0) return set_err(h, LFSR_EINVAL, "n_done must be >= 0");
+  if (!h->y) return set_err(h, LFSR_ESTATE, "lfsr_write_state needs inputs bound by lfsr_init first");
+  hipStream_t s = S(hip_stream);
+  launch_reset(n_done, s, h->b);
+  if (hipMemcpyAsync(h->b.x, d_x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(h->b.wD, d_wd, (size_t)g.sk * g.q * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      (g.sd > 0 && hipMemcpyAsync(h->b.wS[0], d_ws, (size_t)g.sd * g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
+      (d_m && hipMemcpyAsync(h->b.m, d_m, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess))
+    return check_hip(h, "lfsr_write_state copy");
+  h->n_done = n_done;
+  h->bound = true;
+  return check_hip(h, "lfsr_write_state");
+}
+
+lfsr_status lfsr_get_stats(lfsr_handle* h, lfsr_stats* out, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!out) return set_err(h, LFSR_EINVAL, "out is NULL");
+  hipStream_t s = S(hip_stream);
+  DevScalars sc;
+  if (hipMemcpyAsync(&sc, h->b.sc, sizeof(sc), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return check_hip(h, "lfsr_get_stats copy");
+  const int nrow = std::min(h->prm.admm_iters, std::max(h->n_done, 0));
+  if (out->h_hist && nrow > 0 &&
+      hipMemcpyAsync(out->h_hist, h->b.stats, (size_t)nrow * LFSR_NSTAT * sizeof(double), hipMemcpyDeviceToHost,
+                     s) != hipSuccess)
+    return check_hip(h, "lfsr_get_stats copy hist");
+  if (hipStreamSynchronize(s) != hipSuccess) return check_hip(h, "lfsr_get_stats sync");
+  out->iters_run = sc.iters_done;
+  out->cg_steps = sc.cg_steps;
+  out->cg_pi = sc.pi;
+  out->objective = 0.0;
+  out->primal_res = 0.0;
+  const int last = std::min(sc.iters_done, h->prm.admm_iters) - 1;
+  if (last >= 0) {
+    double row[LFSR_NSTAT];
+    if (hipMemcpy(row, h->b.stats + (size_t)last * LFSR_NSTAT, sizeof(row), hipMemcpyDeviceToHost) != hipSuccess)
+      return check_hip(h, "lfsr_get_stats row");
+    out->objective = row[0];
+    out->primal_res = row[1];
+  }
+  if (sc.err_flags & 1) return set_err(h, LFSR_ENONFINITE, "non-finite value in the LR views, disparity or occlusion map");
+  if (sc.err_flags & 2) return set_err(h, LFSR_EINVAL, "|disparity| exceeds disp_bound");
+  return check_hip(h, "lfsr_get_stats");
+}
+
+lfsr_status lfsr_solve(lfsr_handle* h, const float* d_lr, const float* d_disp, const float* d_occ,
+                       const float* d_x0, float* d_hr_out, lfsr_stats* h_stats, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_hr_out) return set_err(h, LFSR_EINVAL, "d_hr_out is NULL");
+  st = lfsr_init(h, d_lr, d_disp, d_occ, d_x0, hip_stream);
+  if (st) return st;
+  st = lfsr_iterate(h, h->prm.admm_iters, hip_stream);
+  if (st) return st;
+  if (hipMemcpyAsync(d_hr_out, h->b.x, (size_t)h->plan.g.p * 4, hipMemcpyDeviceToDevice, S(hip_stream)) !=
+      hipSuccess)
+    return check_hip(h, "lfsr_solve copy out");
+  if (h_stats) return lfsr_get_stats(h, h_stats, hip_stream);
+  return check_hip(h, "lfsr_solve");
+}
+
+lfsr_status lfsr_forward(lfsr_handle* h, const float* d_x, const float* d_disp, float* d_lr_out, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_x || !d_disp || !d_lr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  launch_forward(h->plan.g, d_x, d_disp, d_lr_out, S(hip_stream), h->b, 0);
+  return check_hip(h, "lfsr_forward");
+}
+
+lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp, float* d_hr_out, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_lr || !d_disp || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  launch_adjoint(h->plan.g, d_lr, d_disp, S(hip_stream), h->b, 0);
+  launch_merge(h->plan.g, d_hr_out, S(hip_stream), h->b);
+  return check_hip(h, "lfsr_adjoint");
+}
+
+lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, const float* d_m, float* d_out,
+                        void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_p || !d_disp || !d_m || !d_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  const Geom& g = h->plan.g;
+  hipStream_t s = S(hip_stream);
+  launch_forward(g, d_p, d_disp, h->b.lr, s, h->b, 0);
+  launch_adjoint(g, h->b.lr, d_disp, s, h->b, 0);
+  launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0);
+  return check_hip(h, "lfsr_normal");
+}
+
+lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_occ, float* d_m_out, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_x || !d_m_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  launch_edge(h->plan.g, d_x, d_occ, d_m_out, S(hip_stream), h->b, 0);
+  return check_hip(h, "lfsr_edge_weight");
+}
+
+lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_lr_view || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  launch_bicubic(h->plan.g, d_lr_view, d_hr_out, S(hip_stream));
+  return check_hip(h, "lfsr_bicubic");
+}
+
+}  // extern "C"

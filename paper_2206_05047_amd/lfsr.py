@@ -1,0 +1,261 @@
+"""Python binding of the C ABI in include/lfsr.h (ctypes).
+
+Argument marshalling only: torch tensors provide device memory and streams,
+every step of the solver runs in the HIP library.  There is no fallback: if
+the library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch  # imported before the library so both share torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblfsr.so")
+_lib = None
+
+LFSR_OK, LFSR_EINVAL, LFSR_ENOMEM, LFSR_EDEVICE, LFSR_ESTATE, LFSR_ENONFINITE, LFSR_EBUSY = 0, -1, -2, -3, -4, -5, -6
+LFSR_F32, LFSR_F16, LFSR_BF16 = 0, 1, 2
+LFSR_NSTAT = 6
+
+EXPORTS = [
+    "lfsr_workspace_bytes", "lfsr_create", "lfsr_destroy", "lfsr_last_error", "lfsr_solve", "lfsr_init",
+    "lfsr_iterate", "lfsr_read_state", "lfsr_write_state", "lfsr_get_stats", "lfsr_forward", "lfsr_adjoint",
+    "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic",
+]
+
+
+class lfsr_params(ctypes.Structure):
+    _fields_ = [
+        ("ang_rows", ctypes.c_int32), ("ang_cols", ctypes.c_int32),
+        ("lr_h", ctypes.c_int32), ("lr_w", ctypes.c_int32),
+        ("scale", ctypes.c_int32), ("n_disp", ctypes.c_int32),
+        ("blur_size", ctypes.c_int32), ("blur_sigma", ctypes.c_float),
+        ("lambda1", ctypes.c_float), ("lambda2", ctypes.c_float),
+        ("nltv_window", ctypes.c_int32),
+        ("sigma_s", ctypes.c_float), ("sigma_e", ctypes.c_float),
+        ("reweight", ctypes.c_int32),
+        ("admm_penalty", ctypes.c_float),
+        ("admm_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+        ("cg_tol", ctypes.c_float), ("stop_tol", ctypes.c_float),
+        ("disp_bound", ctypes.c_float),
+        ("storage", ctypes.c_int32),
+    ]
+
+
+class lfsr_stats(ctypes.Structure):
+    _fields_ = [
+        ("iters_run", ctypes.c_int32), ("cg_steps", ctypes.c_int32),
+        ("objective", ctypes.c_double), ("primal_res", ctypes.c_double), ("cg_pi", ctypes.c_double),
+        ("h_hist", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class LfsrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lfsr error {code}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load liblfsr.so (built by paper_2206_05047_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() first")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V, F, I = ctypes.POINTER(lfsr_params), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32
+    H = ctypes.c_void_p
+    lib.lfsr_workspace_bytes.argtypes = [P]
+    lib.lfsr_workspace_bytes.restype = ctypes.c_size_t
+    lib.lfsr_create.argtypes = [P, V, ctypes.c_size_t, ctypes.POINTER(H)]
+    lib.lfsr_create.restype = I
+    lib.lfsr_destroy.argtypes = [H]
+    lib.lfsr_destroy.restype = None
+    lib.lfsr_last_error.argtypes = [H]
+    lib.lfsr_last_error.restype = ctypes.c_char_p
+    lib.lfsr_solve.argtypes = [H, F, F, F, F, F, ctypes.POINTER(lfsr_stats), V]
+    lib.lfsr_solve.restype = I
+    lib.lfsr_init.argtypes = [H, F, F, F, F, V]
+    lib.lfsr_init.restype = I
+    lib.lfsr_iterate.argtypes = [H, I, V]
+    lib.lfsr_iterate.restype = I
+    lib.lfsr_read_state.argtypes = [H, F, F, F, F, V]
+    lib.lfsr_read_state.restype = I
+    lib.lfsr_write_state.argtypes = [H, F, F, F, F, I, V]
+    lib.lfsr_write_state.restype = I
+    lib.lfsr_get_stats.argtypes = [H, ctypes.POINTER(lfsr_stats), V]
+    lib.lfsr_get_stats.restype = I
+    for name in ("lfsr_forward", "lfsr_adjoint"):
+        getattr(lib, name).argtypes = [H, F, F, F, V]
+        getattr(lib, name).restype = I
+    lib.lfsr_normal.argtypes = [H, F, F, F, F, V]
+    lib.lfsr_normal.restype = I
+    lib.lfsr_edge_weight.argtypes = [H, F, F, F, V]
+    lib.lfsr_edge_weight.restype = I
+    lib.lfsr_bicubic.argtypes = [H, F, F, V]
+    lib.lfsr_bicubic.restype = I
+    _lib = lib
+    return lib
+
+
+def last_error(handle=None) -> str:
+    return load().lfsr_last_error(handle).decode()
+
+
+def make_params(cfg: dict, **over) -> lfsr_params:
+    """lfsr_params from a workload dict (keys as in synth.CONFIGS)."""
+    c = dict(cfg)
+    c.update(over)
+    return lfsr_params(
+        ang_rows=c["U"], ang_cols=c["V"], lr_h=c["sy"], lr_w=c["sx"], scale=c["zeta"],
+        n_disp=c.get("n_disp", 1), blur_size=c["kb"], blur_sigma=c["sigma_b"],
+        lambda1=c["lambda1"], lambda2=c["lambda2"], nltv_window=c["win"],
+        sigma_s=c["sigma_s"], sigma_e=c["sigma_e"], reweight=c.get("reweight", 1),
+        admm_penalty=c["theta"], admm_iters=c["n_iter"], cg_iters=c["cg_iter"],
+        cg_tol=c.get("cg_tol", 0.0), stop_tol=c.get("stop_tol", 0.0),
+        disp_bound=c.get("disp_bound", 2.0), storage=c.get("storage", LFSR_F32),
+    )
+
+
+def workspace_bytes(params: lfsr_params) -> int:
+    n = load().lfsr_workspace_bytes(ctypes.byref(params))
+    if n == 0:
+        raise LfsrError(LFSR_EINVAL, last_error())
+    return int(n)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float32, (t.device, t.dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Solver:
+    """One lfsr_handle over a torch-allocated workspace."""
+
+    def __init__(self, params: lfsr_params, device="cuda"):
+        self.lib = load()
+        self.params = params
+        self.device = torch.device(device)
+        self.bytes = workspace_bytes(params)
+        self.workspace = torch.empty(self.bytes, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.lfsr_create(ctypes.byref(params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                         self.bytes, ctypes.byref(h)), None)
+        self.handle = h
+        p = params
+        self.H, self.W = p.scale * p.lr_h, p.scale * p.lr_w
+        self.sk = p.ang_rows * p.ang_cols
+        self.sd = p.nltv_window * p.nltv_window - 1
+
+    def _check(self, code, h):
+        if code != LFSR_OK:
+            raise LfsrError(code, self.lib.lfsr_last_error(h).decode())
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.lfsr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- tensor helpers
+    def _empty(self, *shape):
+        return torch.empty(shape, dtype=torch.float32, device=self.device)
+
+    # -- C ABI, one method per entry point
+    def lfsr_solve(self, y, disp, occ=None, x0=None, out=None, stats=True, stream=None):
+        out = self._empty(self.H, self.W) if out is None else out
+        st, hist = self._stats_buf() if stats else (None, None)
+        self._check(self.lib.lfsr_solve(self.handle, _ptr(y), _ptr(disp), _ptr(occ), _ptr(x0), _ptr(out),
+                                        ctypes.byref(st) if st is not None else None, _stream(stream)), self.handle)
+        return out, (self._stats_dict(st, hist) if stats else None)
+
+    def lfsr_init(self, y, disp, occ=None, x0=None, stream=None):
+        self._bound = (y, disp, occ, x0)  # keep the inputs alive while bound
+        self._check(self.lib.lfsr_init(self.handle, _ptr(y), _ptr(disp), _ptr(occ), _ptr(x0), _stream(stream)),
+                    self.handle)
+
+    def lfsr_iterate(self, count=1, stream=None):
+        self._check(self.lib.lfsr_iterate(self.handle, int(count), _stream(stream)), self.handle)
+
+    def lfsr_read_state(self, stream=None):
+        p = self.params
+        x = self._empty(self.H, self.W)
+        wd = self._empty(self.sk, p.lr_h, p.lr_w)
+        ws = self._empty(max(self.sd, 0), self.H, self.W)
+        m = self._empty(self.H, self.W)
+        self._check(self.lib.lfsr_read_state(self.handle, _ptr(x), _ptr(wd), _ptr(ws) if self.sd > 0 else None,
+                                             _ptr(m), _stream(stream)), self.handle)
+        return {"x": x, "wD": wd, "wS": ws, "m": m}
+
+    def lfsr_write_state(self, x, wd, ws, m, n_done, stream=None):
+        self._check(self.lib.lfsr_write_state(self.handle, _ptr(x), _ptr(wd), _ptr(ws) if self.sd > 0 else None,
+                                              _ptr(m), int(n_done), _stream(stream)), self.handle)
+
+    def _stats_buf(self):
+        hist = (ctypes.c_double * (self.params.admm_iters * LFSR_NSTAT))()
+        st = lfsr_stats()
+        st.h_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        return st, hist
+
+    def _stats_dict(self, st, hist):
+        import numpy as np
+        n = min(st.iters_run, self.params.admm_iters)
+        h = np.frombuffer(hist, dtype=np.float64).reshape(self.params.admm_iters, LFSR_NSTAT)[:n].copy()
+        return {"iters_run": st.iters_run, "cg_steps": st.cg_steps, "objective": st.objective,
+                "primal_res": st.primal_res, "cg_pi": st.cg_pi, "hist": h}
+
+    def lfsr_get_stats(self, stream=None):
+        st, hist = self._stats_buf()
+        self._check(self.lib.lfsr_get_stats(self.handle, ctypes.byref(st), _stream(stream)), self.handle)
+        return self._stats_dict(st, hist)
+
+    def lfsr_forward(self, x, disp, out=None, stream=None):
+        p = self.params
+        out = self._empty(self.sk, p.lr_h, p.lr_w) if out is None else out
+        self._check(self.lib.lfsr_forward(self.handle, _ptr(x), _ptr(disp), _ptr(out), _stream(stream)), self.handle)
+        return out
+
+    def lfsr_adjoint(self, lr, disp, out=None, stream=None):
+        out = self._empty(self.H, self.W) if out is None else out
+        self._check(self.lib.lfsr_adjoint(self.handle, _ptr(lr), _ptr(disp), _ptr(out), _stream(stream)), self.handle)
+        return out
+
+    def lfsr_normal(self, pvec, disp, m, out=None, stream=None):
+        out = self._empty(self.H, self.W) if out is None else out
+        self._check(self.lib.lfsr_normal(self.handle, _ptr(pvec), _ptr(disp), _ptr(m), _ptr(out), _stream(stream)),
+                    self.handle)
+        return out
+
+    def lfsr_edge_weight(self, x, occ=None, out=None, stream=None):
+        out = self._empty(self.H, self.W) if out is None else out
+        self._check(self.lib.lfsr_edge_weight(self.handle, _ptr(x), _ptr(occ), _ptr(out), _stream(stream)),
+                    self.handle)
+        return out
+
+    def lfsr_bicubic(self, lr_view, out=None, stream=None):
+        out = self._empty(self.H, self.W) if out is None else out
+        self._check(self.lib.lfsr_bicubic(self.handle, _ptr(lr_view), _ptr(out), _stream(stream)), self.handle)
+        return out
+
+
+def disp_bound_for(disp, margin=1.0) -> float:
+    """A disp_bound covering a disparity map (host-side helper)."""
+    import numpy as np
+    m = float(np.max(np.abs(np.asarray(disp)))) if np.asarray(disp).size else 0.0
+    return max(m * margin, 1e-3) if math.isfinite(m) else float("nan")

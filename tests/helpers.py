@@ -1,0 +1,39 @@
+"""Shared test helpers: seeded problem cases built from the synthetic generator
+and the oracle's forward model (never from the HIP path)."""
+import numpy as np
+
+import oracle
+from paper_2206_05047_amd import synth
+
+# A ragged case: several forward/adjoint tiles with partial tails in both
+# directions, a non-square angular grid, scale 3 and smooth + stepped disparity.
+RAGGED = dict(synth.CONFIGS["c1"], name="ragged", U=3, V=5, sy=37, sx=29, zeta=3, kb=7, sigma_b=1.3, win=5,
+              n_iter=6, seed=11, noise_sigma=0.03, impulse_frac=0.1, impulse="salt_pepper", scene="layers",
+              n_layers=5, disp_max=1.5)
+
+# Degenerate shapes: one view, no blur, no regulariser, scale 1.
+SINGLE = dict(synth.CONFIGS["c1"], name="single", U=1, V=1, sy=21, sx=19, zeta=1, kb=1, sigma_b=1.0, win=1,
+              n_iter=4, seed=12, scene="layers", n_layers=3, disp_max=1.0)
+
+CASES = {"c1": synth.CONFIGS["c1"], "ragged": RAGGED, "single": SINGLE}
+
+
+def disp_bound(cfg):
+    return float(cfg.get("disp_max", 2.0))
+
+
+def make_case(cfg, seed=None):
+    """Seeded scene -> LR views through the oracle's forward model -> noise."""
+    o = oracle.Oracle(cfg)
+    sc = synth.make_scene(cfg, seed)
+    nz = synth.make_noise(cfg, seed)
+    y = synth.degrade(o.forward(sc["x_gt"], sc["disp"]), nz)
+    return {"cfg": cfg, "oracle": o, "x_gt": sc["x_gt"], "disp": sc["disp"], "y": y}
+
+
+def rel_err(a, ref):
+    """max |a - ref| / max |ref| (elementwise parity measure)."""
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    den = np.abs(ref).max()
+    return float(np.abs(a - ref).max() / (den if den > 0 else 1.0))

@@ -1,0 +1,214 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Tolerances are relative to the FP32 arithmetic of the
+kernels: single operators 1e-5 (max-abs relative), whole solves 1e-4 relative
+L2 (the bar the method's FP32 solver must meet against the FP64 oracle)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from helpers import CASES, disp_bound, make_case, rel_err  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2206_05047_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+OP_TOL = 2e-5
+SOLVE_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def lfsr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_05047_amd import lfsr as mod
+    mod.load()
+    return mod
+
+
+def _solver(lfsr, cfg, **over):
+    p = lfsr.make_params(cfg, disp_bound=disp_bound(cfg), **over)
+    return lfsr.Solver(p)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+
+
+def _n(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    print(f"[case {request.param}]", flush=True)
+    return make_case(CASES[request.param])
+
+
+def test_forward_matches_oracle(lfsr, case):
+    s = _solver(lfsr, case["cfg"])
+    o = case["oracle"]
+    x = np.random.default_rng(1).uniform(0, 1, o.hr_shape).astype(np.float32)
+    got = _n(s.lfsr_forward(_t(x), _t(case["disp"])))
+    ref = o.forward(x, case["disp"])
+    assert rel_err(got, ref) < OP_TOL
+
+
+def test_adjoint_matches_oracle(lfsr, case):
+    s = _solver(lfsr, case["cfg"])
+    o = case["oracle"]
+    e = np.random.default_rng(2).standard_normal(o.lr_shape).astype(np.float32)
+    got = _n(s.lfsr_adjoint(_t(e), _t(case["disp"])))
+    ref = o.adjoint(e, case["disp"])
+    assert rel_err(got, ref) < OP_TOL
+
+
+def test_normal_operator_matches_oracle(lfsr, case):
+    s = _solver(lfsr, case["cfg"])
+    o = case["oracle"]
+    rng = np.random.default_rng(3)
+    pv = rng.standard_normal(o.hr_shape).astype(np.float32)
+    m = rng.uniform(0.2, 1.0, o.hr_shape).astype(np.float32)
+    got = _n(s.lfsr_normal(_t(pv), _t(case["disp"]), _t(m)))
+    ref = o.normal_apply(case["disp"], m, pv)
+    assert rel_err(got, ref) < OP_TOL
+
+
+def test_edge_weight_and_bicubic_match_oracle(lfsr, case):
+    s = _solver(lfsr, case["cfg"])
+    o = case["oracle"]
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 1, o.hr_shape).astype(np.float32)
+    occ = rng.uniform(0.3, 1.0, o.hr_shape).astype(np.float32)
+    assert rel_err(_n(s.lfsr_edge_weight(_t(x), _t(occ))), o.edge_weight(x, occ)) < OP_TOL
+    assert rel_err(_n(s.lfsr_edge_weight(_t(x))), o.edge_weight(x)) < OP_TOL
+    lr = case["y"][o.pb.sk // 2]
+    assert rel_err(_n(s.lfsr_bicubic(_t(lr))), o.bicubic(lr)) < OP_TOL
+
+
+def test_one_iteration_state_matches_oracle(lfsr, case):
+    """After one ADMM iteration: both duals (local functions of x0), the weight
+    map, and x^(1) (through the CG x-step)."""
+    cfg = case["cfg"]
+    s = _solver(lfsr, cfg)
+    o = case["oracle"]
+    s.lfsr_init(_t(case["y"]), _t(case["disp"]))
+    s.lfsr_iterate(1)
+    st = s.lfsr_read_state()
+    ref = o.init_state(case["y"])
+    stats = o.iterate(ref, case["y"], case["disp"], count=1)
+    assert rel_err(_n(st["m"]), ref["m"]) < OP_TOL
+    assert rel_err(_n(st["wD"]), ref["wD"]) < OP_TOL
+    if o.pb.sd > 0:
+        assert rel_err(_n(st["wS"]), ref["wS"]) < OP_TOL
+    assert synth.rel_l2(_n(st["x"]), ref["x"]) < 1e-5
+    g = s.lfsr_get_stats()
+    assert g["iters_run"] == 1
+    np.testing.assert_allclose(g["hist"][0, [0, 1, 4, 5]], stats[0, [0, 1, 4, 5]], rtol=1e-5, atol=1e-9)
+    assert g["hist"][0, 3] == stats[0, 3]
+
+
+def test_full_solve_matches_oracle(lfsr, case):
+    cfg = case["cfg"]
+    s = _solver(lfsr, cfg)
+    o = case["oracle"]
+    x, stats = s.lfsr_solve(_t(case["y"]), _t(case["disp"]))
+    xr, sr = o.solve(case["y"], case["disp"])
+    err = synth.rel_l2(_n(x), xr)
+    print(f"rel_l2={err:.3e} psnr_gpu={synth.psnr(_n(x), case['x_gt']):.3f} "
+          f"psnr_orc={synth.psnr(xr, case['x_gt']):.3f}", flush=True)
+    assert err < SOLVE_TOL
+    assert stats["iters_run"] == cfg["n_iter"]
+    np.testing.assert_allclose(stats["hist"][:, 0], sr[:, 0], rtol=1e-4)
+
+
+def test_solve_with_occlusion_and_x0(lfsr):
+    case = make_case(CASES["ragged"])
+    cfg, o = case["cfg"], case["oracle"]
+    rng = np.random.default_rng(5)
+    occ = rng.uniform(0.4, 1.0, o.hr_shape).astype(np.float32)
+    x0 = rng.uniform(0, 1, o.hr_shape).astype(np.float32)
+    s = _solver(lfsr, cfg)
+    x, _ = s.lfsr_solve(_t(case["y"]), _t(case["disp"]), occ=_t(occ), x0=_t(x0))
+    xr, _ = o.solve(case["y"], case["disp"], occ=occ, x0=x0)
+    assert synth.rel_l2(_n(x), xr) < SOLVE_TOL
+
+
+def test_fixed_weights_and_l1_only(lfsr):
+    case = make_case(CASES["c1"])
+    cfg = dict(case["cfg"], reweight=0, lambda2=0.0)
+    o = oracle.Oracle(cfg)
+    s = _solver(lfsr, cfg)
+    x, _ = s.lfsr_solve(_t(case["y"]), _t(case["disp"]))
+    xr, _ = o.solve(case["y"], case["disp"])
+    assert synth.rel_l2(_n(x), xr) < SOLVE_TOL
+
+
+def test_resume_equals_uninterrupted(lfsr):
+    case = make_case(CASES["ragged"])
+    cfg = case["cfg"]
+    y, d = _t(case["y"]), _t(case["disp"])
+    a = _solver(lfsr, cfg)
+    a.lfsr_init(y, d)
+    a.lfsr_iterate(5)
+    sa = a.lfsr_read_state()
+    b = _solver(lfsr, cfg)
+    b.lfsr_init(y, d)
+    b.lfsr_iterate(2)
+    sb = b.lfsr_read_state()
+    c = _solver(lfsr, cfg)
+    c.lfsr_init(y, d)
+    c.lfsr_write_state(sb["x"], sb["wD"], sb["wS"], sb["m"], 2)
+    c.lfsr_iterate(3)
+    sc = c.lfsr_read_state()
+    for key in ("x", "wD", "wS", "m"):
+        np.testing.assert_array_equal(_n(sa[key]), _n(sc[key]))
+
+
+def test_deterministic_bits(lfsr):
+    case = make_case(CASES["ragged"])
+    s = _solver(lfsr, case["cfg"])
+    y, d = _t(case["y"]), _t(case["disp"])
+    x1, _ = s.lfsr_solve(y, d)
+    x1 = _n(x1)
+    x2, _ = s.lfsr_solve(y, d)
+    np.testing.assert_array_equal(x1, _n(x2))
+
+
+def test_cg_tolerance_and_stop_test(lfsr):
+    case = make_case(CASES["c1"])
+    cfg = dict(case["cfg"], cg_tol=1e-3, stop_tol=0.5, n_iter=20)
+    o = oracle.Oracle(cfg)
+    s = _solver(lfsr, cfg)
+    x, st = s.lfsr_solve(_t(case["y"]), _t(case["disp"]))
+    # oracle replay: the same CG tolerance, stopping at the first n with res_n <= tol * res_1
+    ref = o.init_state(case["y"])
+    res1, n_run = None, 0
+    for n in range(cfg["n_iter"]):
+        row = o.iterate(ref, case["y"], case["disp"], count=1)[0]
+        n_run += 1
+        res1 = row[1] if res1 is None else res1
+        if row[1] <= 0.5 * res1:
+            break
+    assert st["iters_run"] == n_run < cfg["n_iter"]
+    assert synth.rel_l2(_n(x), ref["x"]) < SOLVE_TOL
+
+
+def test_input_errors_reported(lfsr):
+    case = make_case(CASES["c1"])
+    s = _solver(lfsr, case["cfg"])
+    y = case["y"].copy()
+    y[0, 3, 4] = np.nan
+    s.lfsr_init(_t(y), _t(case["disp"]))
+    with pytest.raises(lfsr.LfsrError) as ei:
+        s.lfsr_get_stats()
+    assert ei.value.code == lfsr.LFSR_ENONFINITE
+    d = case["disp"].copy()
+    d[5, 5] = 3.5  # beyond disp_bound = 2: the warp clamps, the check reports it
+    s.lfsr_init(_t(case["y"]), _t(d))
+    s.lfsr_iterate(1)
+    with pytest.raises(lfsr.LfsrError) as ei:
+        s.lfsr_get_stats()
+    assert ei.value.code == lfsr.LFSR_EINVAL
