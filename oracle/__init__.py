@@ -49,7 +49,7 @@ class OrcParams(ctypes.Structure):
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle with gcc (plain IEEE arithmetic, OpenMP)."""
-    from .build import build_oracle
+    from .buildlib import build_oracle
 
     return build_oracle(verbose=verbose)
 
