@@ -26,6 +26,7 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--cpu-iters", type=int, default=2, help="ADMM iterations of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iters", type=int, default=0, help="override the ADMM iteration count (profiling only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -39,6 +40,8 @@ def main():
 
     torch.cuda.set_device(0)
     cfg = synth.config(args.config)
+    if args.iters > 0:
+        cfg["n_iter"] = args.iters
     sc = synth.make_scene(cfg)
     noise = synth.make_noise(cfg)
     bound = float(np.abs(sc["disp"]).max())

@@ -18,8 +18,8 @@ thread_local std::string g_thread_err = "no error";
 
 struct Plan {
   Geom g;
-  size_t off_x, off_m, off_vs, off_r, off_pv, off_hp, off_wd, off_ws0, off_ws1, off_lr, off_adj, off_part,
-      off_stats, off_sc;
+  size_t off_x, off_m, off_vs, off_r, off_pv, off_hp, off_wd, off_ws0, off_ws1, off_lr, off_adj, off_pwzd,
+      off_ptv, off_prr0, off_prr1, off_pphp, off_pmax, off_stats, off_sc;
   size_t bytes;
 };
 
@@ -33,29 +33,32 @@ bool fail(std::string* err, const char* msg) {
 // Tiling for the forward and adjoint kernels; false if the warp halo is too
 // large for any LDS tile.
 bool choose_tiles(Geom& g, std::string* err) {
-  // forward: LR tile, largest of 16x16 / 16x8 / 8x8 / 8x4 / 4x4 whose LDS fits
-  const int fcand[5][2] = {{16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 4}};
+  // forward: the largest LR tile whose LDS and per-thread slots fit
+  const int fcand[6][2] = {{16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 4}, {4, 2}};
   bool ok = false;
   for (auto& c : fcand) {
     g.f_tly = c[0];
     g.f_tlx = c[1];
-    if (forward_lds(g) <= 60 * 1024) {
+    if (forward_tile_ok(g)) {
       ok = true;
       break;
     }
   }
   if (!ok) return fail(err, "disp_bound too large: the forward warp halo does not fit in LDS");
   const long long ftiles = (long long)((g.sy + g.f_tly - 1) / g.f_tly) * ((g.sx + g.f_tlx - 1) / g.f_tlx);
+  // views per block: whole angular rows when that still gives >= ~2048 blocks
+  // (the vertical warp coordinate is then computed once per row)
   long long vpb = (ftiles * g.sk + 3071) / 3072;
   if (vpb < 1) vpb = 1;
+  if (vpb >= g.V) vpb = (vpb / g.V) * g.V;
+  else if (ftiles * ((g.sk + g.V - 1) / g.V) >= 2048) vpb = g.V;
   if (vpb > g.sk) vpb = g.sk;
   g.f_vpb = (int)vpb;
 
-  // adjoint: prefer >= 1024 tiles; HR tile must be at least the halo and
-  // hold <= kAdjMaxPix pixels per thread
-  const int acand[5][2] = {{16, 8}, {8, 8}, {8, 4}, {4, 4}, {4, 2}};
+  // adjoint: prefer >= 1024 tiles; the HR tile must be at least the halo
+  const int acand[6][2] = {{16, 8}, {8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}};
   int best = -1;
-  for (int ci = 0; ci < 5; ++ci) {
+  for (int ci = 0; ci < 6; ++ci) {
     Geom t = g;
     t.a_tly = acand[ci][0];
     t.a_tlx = acand[ci][1];
@@ -63,9 +66,7 @@ bool choose_tiles(Geom& g, std::string* err) {
     t.a_tw = t.a_tlx * g.zeta;
     t.a_ey = t.a_th + 2 * g.halo;
     t.a_ex = t.a_tw + 2 * g.halo;
-    if (t.a_th < g.halo || t.a_tw < g.halo) continue;
-    if ((long long)t.a_th * t.a_tw > (long long)kThreads * kAdjMaxPix) continue;
-    if (adjoint_lds(t) > 60 * 1024) continue;
+    if (!adjoint_tile_ok(t)) continue;
     const long long nt = (long long)((g.sy + t.a_tly - 1) / t.a_tly) * ((g.sx + t.a_tlx - 1) / t.a_tlx);
     best = ci;
     if (nt >= 1024) break;
@@ -79,7 +80,10 @@ bool choose_tiles(Geom& g, std::string* err) {
   g.a_ex = g.a_tw + 2 * g.halo;
   g.a_nty = (g.sy + g.a_tly - 1) / g.a_tly;
   g.a_ntx = (g.sx + g.a_tlx - 1) / g.a_tlx;
-  g.a_npix = (g.a_th * g.a_tw + kThreads - 1) / kThreads;
+  g.a_inv_th = (float)(1.0 / g.a_th);
+  g.a_inv_tw = (float)(1.0 / g.a_tw);
+  long long rbk = (g.p + 4 * kThreads - 1) / (4 * kThreads);
+  g.red_blocks = (int)(rbk < kRedBlocks ? (rbk < 1 ? 1 : rbk) : kRedBlocks);
   return true;
 }
 
@@ -159,6 +163,8 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
       const double c = std::exp(-(double)(dy * dy + dx * dx) / (double)p->sigma_s);
       g.cd[d] = (float)c;
       g.cd2[d] = (float)(c * c);
+      g.ody[d] = (signed char)dy;
+      g.odx[d] = (signed char)dx;
     }
   }
   g.lambda1 = p->lambda1;
@@ -167,6 +173,8 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   g.clip = (float)(1.0 / (double)p->admm_penalty);
   g.cA = (float)((double)p->lambda2 + 0.5 * (double)p->admm_penalty * (double)p->lambda1 * p->lambda1);
   g.use_edge = std::isfinite(p->sigma_e) ? 1 : 0;
+  g.reweight = p->reweight;
+  g.n_iter = p->admm_iters;
   g.inv_sigma_e = g.use_edge ? (float)(1.0 / (double)p->sigma_e) : 0.f;
   g.disp_bound = p->disp_bound;
   g.cg_tol = p->cg_tol;
@@ -199,10 +207,12 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   pl->off_adj = take((size_t)g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4);
   {
     const dim3 fg = forward_grid(g), tg = tv_grid(g);
-    size_t nb = (size_t)fg.x * fg.y * fg.z * 3;
-    nb = std::max(nb, (size_t)tg.x * tg.y * 2);
-    nb = std::max(nb, (size_t)kRedBlocks);
-    pl->off_part = take(nb * sizeof(double));
+    pl->off_pwzd = take((size_t)fg.x * fg.y * fg.z * 3 * sizeof(double));
+    pl->off_ptv = take((size_t)tg.x * tg.y * 2 * sizeof(double));
+    pl->off_prr0 = take((size_t)kRedBlocks * sizeof(double));
+    pl->off_prr1 = take((size_t)kRedBlocks * sizeof(double));
+    pl->off_pphp = take((size_t)tg.x * tg.y * sizeof(double));
+    pl->off_pmax = take(std::max((size_t)fg.x * fg.y * fg.z, (size_t)kRedBlocks) * sizeof(float));
   }
   pl->off_stats = take((size_t)p->admm_iters * LFSR_NSTAT * sizeof(double));
   pl->bytes = o;
@@ -255,26 +265,23 @@ hipStream_t S(void* s) { return (hipStream_t)s; }
 void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   const Geom& g = h->plan.g;
   const Bufs& b = h->b;
-  const int n = h->n_done + 1;
-  const int row = std::min(n, h->prm.admm_iters) - 1;
-  double* stats_row = b.stats + (size_t)row * LFSR_NSTAT;
   // weights from x^(n-1) (sec 7.1: recomputed every iteration when reweighting)
-  if (h->prm.reweight || n == 1) launch_edge(g, b.x, h->occ, b.m, s, b, 1);
+  launch_edge(g, b.x, h->occ, b.m, s, b, kGateAdmm | kGateReweight);
   // z/w-steps of both blocks; e and the NLTV divergence feed v
   launch_forward_wzd(g, b.x, h->disp, h->y, s, b);
   if (g.sd > 0) launch_tv(g, s, b);
-  launch_adjoint(g, b.lr, h->disp, s, b, 1);
-  launch_cginit(g, stats_row, s, b);
+  launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm, forward_blocks(g));
+  launch_cginit(g, s, b);
   // x-step: K CG steps on G^T G delta = -v, accumulated straight into x
-  for (int k = 0; k < h->prm.cg_iters; ++k) {
-    launch_forward(g, b.pv, h->disp, b.lr, s, b, 3);
-    launch_adjoint(g, b.lr, h->disp, s, b, 3);
-    launch_hp(g, b.pv, b.m, b.hp, s, b, 3, 1);
-    launch_cgupd(g, s, b);
-    launch_cgp(g, s, b);
+  for (int k = 1; k <= h->prm.cg_iters; ++k) {
+    launch_forward(g, b.pv, h->disp, b.lr, s, b, kGateAdmm | kGateCg);
+    launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g));
+    launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1);
+    launch_cgupd(g, k, s, b);
+    launch_cgp(g, k, s, b);
   }
-  launch_iter_end(g, stats_row, s, b);
-  h->n_done = n;
+  launch_iter_end(g, s, b);
+  h->n_done += 1;
 }
 
 }  // namespace
@@ -320,7 +327,12 @@ lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, l
   h->b.wS[1] = (float*)(w + pl.off_ws1);
   h->b.lr = (float*)(w + pl.off_lr);
   h->b.adj = (float*)(w + pl.off_adj);
-  h->b.part = (double*)(w + pl.off_part);
+  h->b.p_wzd = (double*)(w + pl.off_pwzd);
+  h->b.p_tv = (double*)(w + pl.off_ptv);
+  h->b.p_rr[0] = (double*)(w + pl.off_prr0);
+  h->b.p_rr[1] = (double*)(w + pl.off_prr1);
+  h->b.p_php = (double*)(w + pl.off_pphp);
+  h->b.p_max = (float*)(w + pl.off_pmax);
   h->b.stats = (double*)(w + pl.off_stats);
   h->n_done = 0;
   h->bound = false;
@@ -466,8 +478,10 @@ lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp,
   lfsr_status st = usable(h);
   if (st) return st;
   if (!d_lr || !d_disp || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
-  launch_adjoint(h->plan.g, d_lr, d_disp, S(hip_stream), h->b, 0);
-  launch_merge(h->plan.g, d_hr_out, S(hip_stream), h->b);
+  const Geom& g = h->plan.g;
+  const int npmax = launch_absmax(g, d_lr, (long long)g.sk * g.q, S(hip_stream), h->b);
+  launch_adjoint(g, d_lr, d_disp, S(hip_stream), h->b, 0, npmax);
+  launch_merge(g, d_hr_out, S(hip_stream), h->b);
   return check_hip(h, "lfsr_adjoint");
 }
 
@@ -479,7 +493,7 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   const Geom& g = h->plan.g;
   hipStream_t s = S(hip_stream);
   launch_forward(g, d_p, d_disp, h->b.lr, s, h->b, 0);
-  launch_adjoint(g, h->b.lr, d_disp, s, h->b, 0);
+  launch_adjoint(g, h->b.lr, d_disp, s, h->b, 0, forward_blocks(g));
   launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0);
   return check_hip(h, "lfsr_normal");
 }

@@ -10,9 +10,17 @@ constexpr int kMaxTaps = 31;      // blur size limit
 constexpr int kMaxWin = 15;       // NLTV window limit
 constexpr int kMaxOffsets = kMaxWin * kMaxWin - 1;
 constexpr int kThreads = 256;     // every kernel runs 256-thread (4 x wave64) blocks
-constexpr int kAdjMaxPix = 16;    // HR pixels per thread in the adjoint tile
-constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles
-constexpr int kRedBlocks = 1024;  // grid of the element-wise reduction kernels
+
+// forward operator: blur positions, horizontal-pass outputs per thread
+constexpr int kFwdSlots = 12;     // NY*NX <= 256*kFwdSlots
+constexpr int kFwdHSlots = 5;     // NY*tlx <= 256*kFwdHSlots
+// adjoint: HR pixels, vertical-pass outputs and LR tile values per thread
+constexpr int kAdjSlots = 6;      // TH*TW <= 256*kAdjSlots
+constexpr int kAdjVSlots = 4;     // TH*LX <= 256*kAdjVSlots
+constexpr int kAdjESlots = 2;     // LY*LX <= 256*kAdjESlots
+
+constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles (4 rows per thread)
+constexpr int kRedBlocks = 1024;  // max grid of the element-wise CG kernels (= partials per reduction)
 
 // Problem geometry and model constants, passed by value to every kernel.
 struct Geom {
@@ -24,43 +32,42 @@ struct Geom {
   int win, rw, sd;            // NLTV window, radius, number of offsets
   float cd[kMaxOffsets];      // spatial weight exp(-|d|^2/sigma_s) of offset d
   float cd2[kMaxOffsets];     // its square
+  signed char ody[kMaxOffsets], odx[kMaxOffsets];  // offset d = (dy, dx)
   float lambda1, lambda2;
   float half_theta;           // vartheta / 2
   float clip;                 // 1 / vartheta
   float cA;                   // lambda2 + vartheta lambda1^2 / 2
   float inv_sigma_e;          // 1/sigma_e (0 when the edge weight is off)
   int use_edge;
+  int reweight;
   int halo;                   // warp halo in HR px: ceil(max |theta| * disp_bound) + 1
   float disp_bound;
   float cg_tol;
   float stop_tol;
+  int n_iter;                 // rows of the statistics history
   // forward-operator tiling: LR tile and views per block
   int f_tly, f_tlx, f_vpb;
   // adjoint tiling: LR tile, HR tile, extended (haloed) tile, tile grid
   int a_tly, a_tlx, a_th, a_tw, a_ey, a_ex, a_nty, a_ntx;
-  int a_npix;                 // HR pixels per thread (<= kAdjMaxPix)
+  float a_inv_th, a_inv_tw;   // 1/a_th, 1/a_tw (division-free tile lookup)
+  int red_blocks;             // grid of the element-wise CG kernels
 };
 
-// Device-resident scalars of one handle (lives in the workspace).
+// Device-resident scalars of one handle (lives in the workspace).  Written by
+// block 0 of a kernel and read by later kernels only (no intra-kernel
+// cross-block communication, so no device-scope fences are needed).
 struct DevScalars {
-  double pi;        // CG |r|^2
-  double alpha, beta;
-  double php;       // <p, Hp>
-  double data_abs, data_sq, dwD2;   // wz-step data-block partial results
-  double reg_abs, dwS2;             // wz-step NLTV-block partial results
+  double pi;        // final CG |r|^2 of the current x-step
   double res1;      // primal residual of the first iteration (stop test)
   int res1_set;
   int wcur;         // which NLTV dual buffer holds the current w_S
   int cg_done;      // CG of the current x-step has stopped
+  int cg_steps;     // CG steps taken in the current x-step
   int admm_done;    // stop test met: later iterations are no-ops
   int stop_pending;
-  int cg_steps;
   int iters_done;
   int err_flags;    // bit 0: non-finite input, bit 1: |disp| > disp_bound
-  unsigned counters[16];  // last-block counters, one per reduction site
 };
-
-enum Counter { kCntFwd = 0, kCntTv, kCntInit, kCntHp, kCntUpd, kCntCheck };
 
 // Device pointers of one handle's working set.
 struct Bufs {
@@ -74,33 +81,49 @@ struct Bufs {
   float* wS[2];    // [sd][H][W] NLTV dual, ping-pong
   float* lr;       // [sk][sy][sx] e (wz-step) or t = A p (CG)
   float* adj;      // [a_nty*a_ntx][a_ey][a_ex] per-tile adjoint partial images
-  double* part;    // per-block FP64 partial sums
-  double* stats;   // [admm_iters][6]
+  double* p_wzd;   // [forward blocks][3] data-block partial sums
+  double* p_tv;    // [tv blocks][2] NLTV-block partial sums
+  double* p_rr[2]; // [red_blocks] <r,r> partials (ping-pong over CG steps)
+  double* p_php;   // [tv blocks] <p,Hp> partials
+  float* p_max;    // [max(forward blocks, kRedBlocks)] per-block max |LR| (adjoint fixed-point scale)
+  double* stats;   // [n_iter][6]
   DevScalars* sc;
 };
 
-// Launchers (lfsr_kernels.hip).  gate bit 0: skip after the ADMM stop test
-// fired, bit 1: skip after CG stopped (0 for the plain operator entry points).
+// gate bits of the iteration kernels
+enum : int {
+  kGateAdmm = 1,      // skip once the ADMM stop test has fired
+  kGateCg = 2,        // skip once CG has stopped
+  kGateReweight = 4,  // edge weight: skip when reweight = 0 and this is not the first iteration
+};
+
+// Launchers (lfsr_kernels.hip).
 size_t forward_lds(const Geom& g);
 size_t adjoint_lds(const Geom& g);
 size_t tv_lds(const Geom& g);
+bool forward_tile_ok(const Geom& g);
+bool adjoint_tile_ok(const Geom& g);
 dim3 forward_grid(const Geom& g);
 dim3 adjoint_grid(const Geom& g);
 dim3 tv_grid(const Geom& g);
-unsigned red_blocks(const Geom& g);
 void launch_forward(const Geom& g, const float* src, const float* disp, float* out, hipStream_t s,
                     const Bufs& b, int gate);
 void launch_forward_wzd(const Geom& g, const float* src, const float* disp, const float* y, hipStream_t s,
                         const Bufs& b);
-void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate);
+// npmax: number of per-block maxima of |lr| in b.p_max (forward_blocks(g)
+// after a forward launch, or the return value of launch_absmax)
+void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate,
+                    int npmax);
+int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b);
+int forward_blocks(const Geom& g);
 void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b);
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b);
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot);
-void launch_cginit(const Geom& g, double* stats_row, hipStream_t s, const Bufs& b);
-void launch_cgupd(const Geom& g, hipStream_t s, const Bufs& b);
-void launch_cgp(const Geom& g, hipStream_t s, const Bufs& b);
-void launch_iter_end(const Geom& g, double* stats_row, hipStream_t s, const Bufs& b);
+void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b);
+void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b);
+void launch_cgp(const Geom& g, int step, hipStream_t s, const Bufs& b);
+void launch_iter_end(const Geom& g, hipStream_t s, const Bufs& b);
 void launch_edge(const Geom& g, const float* x, const float* occ, float* m, hipStream_t s, const Bufs& b, int gate);
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s);
 void launch_check(const Geom& g, const float* y, const float* disp, const float* occ, hipStream_t s, const Bufs& b);

@@ -8,20 +8,23 @@
 //    contraction, so there is no MFMA; the warp/blur stencils are LDS-staged
 //    and the dual-field streams are coalesced row-major passes.
 //  * Forward operator: one block owns an LR tile and a group of views.  The HR
-//    source tile (plus the blur radius and the warp halo) is staged in LDS once
-//    and reused by every view of the group.  Per view the bilinear warp is
-//    evaluated at every HR position the blur reads, then the separable blur is
+//    source tile (plus blur radius and warp halo) is staged in LDS once and
+//    reused by every view of the group.  Each thread keeps the disparity and
+//    LDS offset of its blur positions in registers; per view it issues all of
+//    its bilinear gathers before any LDS store, then the separable blur is
 //    evaluated only at the lattice points the decimation keeps.
-//  * Adjoint: one block owns an HR tile and all views.  B D^T is applied as a
-//    polyphase separable filter from an LDS copy of the LR tile, and W_k^T as a
-//    scatter with the bilinear weights of W_k into per-wave LDS accumulators
-//    (tile + warp halo).  Each block writes its haloed tile to a partial image;
-//    the consumer kernel sums the (at most 9) overlapping tiles in a fixed
-//    order, so the result is deterministic and needs no global atomics.
-//  * Reductions: per-block FP64 partials, summed in a fixed order by the last
-//    block to finish (device-scope fences + counter).  All control scalars
-//    (CG alpha/beta/pi, stop flags) stay in device memory, so an ADMM
-//    iteration never synchronises with the host.
+//  * Adjoint: one block owns an HR tile and all views.  B D^T is a polyphase
+//    separable filter from an LDS copy of the LR tile (prefetched one view
+//    ahead), and W_k^T the scatter with the bilinear weights of W_k into
+//    per-wave LDS accumulators (tile + warp halo).  Each block writes its
+//    haloed tile to a partial image; consumers sum the overlapping tiles in a
+//    fixed order: deterministic, and no global atomics.
+//  * Reductions: per-block FP64 partials.  The consumer kernel re-reduces them
+//    in a fixed order in every block (partials are visible across the kernel
+//    boundary), so no kernel needs a device-scope fence -- on this part such a
+//    fence writes back the whole L2 of the XCD.  Control scalars (CG alpha,
+//    beta, pi, stop flags) stay on the device: an ADMM iteration never waits
+//    for the host.
 #include "lfsr_internal.h"
 
 namespace lfsr {
@@ -38,62 +41,53 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum N doubles over the block; the result is valid in thread 0.
+// Sum N doubles over the block; every thread receives the totals.
 template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], double* sh /* [4*N] */) {
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
+  __shared__ double sh[4 * N];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
+  __syncthreads();
   if (lane == 0) {
 #pragma unroll
     for (int n = 0; n < N; ++n) sh[wid * N + n] = v[n];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int n = 0; n < N; ++n) v[n] = ((sh[n] + sh[N + n]) + sh[2 * N + n]) + sh[3 * N + n];
-  }
-  __syncthreads();
+  for (int n = 0; n < N; ++n) v[n] = ((sh[n] + sh[N + n]) + sh[2 * N + n]) + sh[3 * N + n];
 }
 
-// Publish this block's partials and report whether it is the last block of the
-// grid to do so.  Release (writers) / acquire (last block) at device scope.
-__device__ __forceinline__ bool last_block(unsigned* counter, unsigned nblocks) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    __threadfence();
-    unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == nblocks - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last != 0;
-}
-
-__device__ __forceinline__ double load_part(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Fixed-order reduction of nb blocks' N partials by the last block.
+// Fixed-order sum of component c of nb per-block partials (stride N); every
+// thread of the block receives the same value.
 template <int N>
-__device__ __forceinline__ void reduce_parts(const double* part, unsigned nb, double (&out)[N], double* sh) {
+__device__ __forceinline__ void sum_parts(const double* __restrict__ part, int nb, double (&out)[N]) {
 #pragma unroll
   for (int n = 0; n < N; ++n) out[n] = 0.0;
-  for (unsigned b = threadIdx.x; b < nb; b += kThreads) {
+  for (int b = threadIdx.x; b < nb; b += kThreads) {
 #pragma unroll
-    for (int n = 0; n < N; ++n) out[n] += load_part(part + (size_t)b * N + n);
+    for (int n = 0; n < N; ++n) out[n] += part[(size_t)b * N + n];
   }
-  block_sum<N>(out, sh);
+  block_sum<N>(out);
 }
 
-__device__ __forceinline__ bool gated(const DevScalars* sc, int gate) {
-  // gate bit 0: skip once the ADMM stop test has fired; bit 1: skip once CG has stopped
-  return ((gate & 1) && sc->admm_done) || ((gate & 2) && sc->cg_done);
+__device__ __forceinline__ bool gated(const DevScalars* sc, const Geom& g, int gate) {
+  if ((gate & kGateAdmm) && sc->admm_done) return true;
+  if ((gate & kGateCg) && sc->cg_done) return true;
+  if ((gate & kGateReweight) && !g.reweight && sc->iters_done != 0) return true;
+  return false;
+}
+
+__device__ __forceinline__ double* stats_row(const Geom& g, double* stats, const DevScalars* sc) {
+  const int r = sc->iters_done < g.n_iter ? sc->iters_done : g.n_iter - 1;
+  return stats + (size_t)r * 6;
 }
 
 // Sum of the per-tile adjoint partial images that cover HR pixel (Y, X).
 __device__ __forceinline__ float adj_merge(const Geom& g, const float* __restrict__ adj, int Y, int X) {
-  const int ty = Y / g.a_th, tx = X / g.a_tw;
+  // (Y + 1/2) / a_th in float: the quotient is at least 1/(2 a_th) away from
+  // an integer and the rounding error is far below that for Y < 2^22
+  const int ty = (int)(((float)Y + 0.5f) * g.a_inv_th), tx = (int)(((float)X + 0.5f) * g.a_inv_tw);
   const int ly = Y - ty * g.a_th, lx = X - tx * g.a_tw;
   const size_t tile = (size_t)g.a_ey * g.a_ex;
   float s = 0.f;
@@ -117,25 +111,26 @@ __device__ __forceinline__ float adj_merge(const Geom& g, const float* __restric
 // Forward operator t_k = D B W_k src for every view (sec 3.1, 4.1).
 // WZD = true fuses the data-block z/w-steps of Algorithm 1: r = t - y,
 // w_D' = clip(lambda1 r + w_D, +-1/vartheta) (= u - prox(u)), and the input of
-// A^T, e = lambda2 r + (vartheta/2) lambda1 (2 w_D' - w_D), written to `out`.
+// A^T, e = lambda2 r + (vartheta/2) lambda1 (2 w_D' - w_D), written to `out`;
+// per-block partials {sum|r|, sum r^2, sum (w_D'-w_D)^2} go to `part`.
 // grid = (ceil(sx/f_tlx), ceil(sy/f_tly), ceil(sk/f_vpb)).
 template <bool WZD>
 __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __restrict__ src,
                                                       const float* __restrict__ disp, float* __restrict__ out,
                                                       const float* __restrict__ y, float* __restrict__ wD,
-                                                      double* __restrict__ part, DevScalars* __restrict__ sc,
-                                                      int gate) {
-  if (gated(sc, gate)) return;
+                                                      double* __restrict__ part, float* __restrict__ pmax,
+                                                      const DevScalars* __restrict__ sc, int gate) {
+  if (gated(sc, g, gate)) return;
   extern __shared__ float smem[];
-  const int zeta = g.zeta, rb = g.rb, h = g.halo;
+  const int zeta = g.zeta, rb = g.rb, h = g.halo, kb = g.kb;
   const int tly = g.f_tly, tlx = g.f_tlx;
   const int NY = (tly - 1) * zeta + 1 + 2 * rb;
   const int NX = (tlx - 1) * zeta + 1 + 2 * rb;
   const int SY = NY + 2 * h, SX = NX + 2 * h;
+  const int NPOS = NY * NX, NH = NY * tlx;
   float* xs = smem;          // [SY][SX] source tile, zero outside the image
-  float* om = xs + SY * SX;  // [NY][NX] disparity at the blur positions
-  float* wv = om + NY * NX;  // [NY][NX] warped values of the current view
-  float* hb = wv + NY * NX;  // [NY][tlx] horizontal blur at lattice columns
+  float* wv = xs + SY * SX;  // [NY][NX] warped values of the current view
+  float* hb = wv + NPOS;     // [NY][tlx] horizontal blur at lattice columns
   const int i0 = blockIdx.y * tly, j0 = blockIdx.x * tlx;
   const int Yp0 = i0 * zeta - rb, Xp0 = j0 * zeta - rb;
   const int tid = threadIdx.x;
@@ -145,66 +140,113 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
     const int Y = Yp0 - h + ty, X = Xp0 - h + tx;
     xs[idx] = (Y >= 0 && Y < g.H && X >= 0 && X < g.W) ? src[(size_t)Y * g.W + X] : 0.f;
   }
-  for (int idx = tid; idx < NY * NX; idx += kThreads) {
-    const int py = idx / NX, px = idx - py * NX;
-    const int Y = Yp0 + py, X = Xp0 + px;
-    om[idx] = (Y >= 0 && Y < g.H && X >= 0 && X < g.W) ? disp[(size_t)Y * g.W + X] : 0.f;
+  // Blur positions of this thread: disparity clamped to +-disp_bound (which
+  // keeps every gather inside the tile) and 0 outside the image, where the
+  // zero tile makes the sample vanish as the zero padding of B requires.
+  float om[kFwdSlots];
+  int base[kFwdSlots];
+  int rbase[kFwdSlots];   // base + row offset of the current angular row
+  float fyv[kFwdSlots];   // vertical bilinear weight of the current angular row
+#pragma unroll
+  for (int s = 0; s < kFwdSlots; ++s) {
+    const int idx = tid + s * kThreads;
+    float w = 0.f;
+    int b = 0;
+    if (idx < NPOS) {
+      const int py = idx / NX, px = idx - py * NX;
+      const int Y = Yp0 + py, X = Xp0 + px;
+      if (Y >= 0 && Y < g.H && X >= 0 && X < g.W)
+        w = fminf(fmaxf(disp[(size_t)Y * g.W + X], -g.disp_bound), g.disp_bound);
+      b = (py + h) * SX + (px + h);
+    }
+    om[s] = w;
+    base[s] = b;
   }
+  int hoff[kFwdHSlots];
+#pragma unroll
+  for (int s = 0; s < kFwdHSlots; ++s) {
+    const int idx = tid + s * kThreads;
+    const int py = idx / tlx, j = idx - py * tlx;
+    hoff[s] = idx < NH ? py * NX + j * zeta : 0;
+  }
+  const int li = tid / tlx, lj = tid - li * tlx;
+  const int oi = i0 + li, oj = j0 + lj;
+  const bool vout = tid < tly * tlx && oi < g.sy && oj < g.sx;
+  const int voff = li * zeta * tlx + lj;
   __syncthreads();
 
   const int k0 = blockIdx.z * g.f_vpb;
   const int k1 = min(g.sk, k0 + g.f_vpb);
-  const float hmin = (float)(-h), hmax = (float)(h - 1);
   double s_abs = 0.0, s_sq = 0.0, s_dw = 0.0;
+  float vmax = 0.f;
   for (int k = k0; k < k1; ++k) {
-    const float tau = (float)(k / g.V - (g.U - 1) / 2);
-    const float rho = (float)(k % g.V - (g.V - 1) / 2);
-    // W_k at every HR position the blur reads; zero outside the image
-    for (int idx = tid; idx < NY * NX; idx += kThreads) {
-      const int py = idx / NX, px = idx - py * NX;
-      const int Y = Yp0 + py, X = Xp0 + px;
-      float val = 0.f;
-      if (Y >= 0 && Y < g.H && X >= 0 && X < g.W) {
-        const float w = om[idx];
-        const float sy = tau * w, sx = rho * w;
-        float fy0 = floorf(sy), fx0 = floorf(sx);
-        const float fy = sy - fy0, fx = sx - fx0;
-        fy0 = fminf(fmaxf(fy0, hmin), hmax);  // memory safety only: |disp| <= disp_bound keeps it in range
-        fx0 = fminf(fmaxf(fx0, hmin), hmax);
-        const float* s = xs + (py + h + (int)fy0) * SX + (px + h + (int)fx0);
-        const float a = s[0], b = s[1], c = s[SX], d = s[SX + 1];
-        const float top = fmaf(fx, b - a, a);
-        const float bot = fmaf(fx, d - c, c);
-        val = fmaf(fy, bot - top, top);
+    const int ka = k / g.V, kc = k - ka * g.V;
+    const float rho = (float)(kc - (g.V - 1) / 2);
+    if (k == k0 || kc == 0) {  // the vertical warp coordinate is shared by an angular row
+      const float tau = (float)(ka - (g.U - 1) / 2);
+#pragma unroll
+      for (int s = 0; s < kFwdSlots; ++s) {
+        const float sy = tau * om[s];
+        const float fy0 = floorf(sy);
+        fyv[s] = sy - fy0;
+        rbase[s] = base[s] + (int)fy0 * SX;
       }
-      wv[idx] = val;
+    }
+    const size_t o = (size_t)k * g.q + (size_t)oi * g.sx + oj;
+    float yv = 0.f, w0 = 0.f;
+    if (WZD && vout) {  // issued early; consumed after the two LDS passes
+      yv = y[o];
+      w0 = wD[o];
+    }
+    // W_k at every blur position of this thread: all gathers, then all stores
+    float val[kFwdSlots];
+#pragma unroll
+    for (int s = 0; s < kFwdSlots; ++s) {
+      const float sx = rho * om[s];
+      const float fx0 = floorf(sx);
+      const float fx = sx - fx0;
+      const int off = rbase[s] + (int)fx0;
+      const float a = xs[off], b = xs[off + 1], c = xs[off + SX], d = xs[off + SX + 1];
+      const float top = fmaf(fx, b - a, a);
+      const float bot = fmaf(fx, d - c, c);
+      val[s] = fmaf(fyv[s], bot - top, top);
+    }
+#pragma unroll
+    for (int s = 0; s < kFwdSlots; ++s) {
+      const int idx = tid + s * kThreads;
+      if (idx < NPOS) wv[idx] = val[s];
     }
     __syncthreads();
     // B, horizontal pass, only at the lattice columns D keeps
-    for (int idx = tid; idx < NY * tlx; idx += kThreads) {
-      const int py = idx / tlx, j = idx - py * tlx;
-      const float* s = wv + py * NX + j * zeta;
-      float acc = 0.f;
-      for (int b = 0; b < g.kb; ++b) acc = fmaf(g.g[b], s[b], acc);
-      hb[idx] = acc;
+    float hsum[kFwdHSlots];
+#pragma unroll
+    for (int s = 0; s < kFwdHSlots; ++s) hsum[s] = 0.f;
+#pragma unroll 4
+    for (int b = 0; b < kb; ++b) {
+      const float gb = g.g[b];
+#pragma unroll
+      for (int s = 0; s < kFwdHSlots; ++s) hsum[s] = fmaf(gb, wv[hoff[s] + b], hsum[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < kFwdHSlots; ++s) {
+      const int idx = tid + s * kThreads;
+      if (idx < NH) hb[idx] = hsum[s];
     }
     __syncthreads();
     // B, vertical pass, only at the lattice rows; then the fused epilogue
-    for (int idx = tid; idx < tly * tlx; idx += kThreads) {
-      const int li = idx / tlx, lj = idx - li * tlx;
-      const int i = i0 + li, j = j0 + lj;
-      if (i >= g.sy || j >= g.sx) continue;
-      const float* s = hb + li * zeta * tlx + lj;
+    if (vout) {
       float t = 0.f;
-      for (int a = 0; a < g.kb; ++a) t = fmaf(g.g[a], s[a * tlx], t);
-      const size_t o = (size_t)k * g.q + (size_t)i * g.sx + j;
+#pragma unroll 4
+      for (int a = 0; a < kb; ++a) t = fmaf(g.g[a], hb[voff + a * tlx], t);
       if constexpr (!WZD) {
         out[o] = t;
+        vmax = fmaxf(vmax, fabsf(t));
       } else {
-        const float r = t - y[o];
-        const float w0 = wD[o];
+        const float r = t - yv;
         const float wn = clipf(fmaf(g.lambda1, r, w0), g.clip);
-        out[o] = g.lambda2 * r + g.half_theta * g.lambda1 * (2.f * wn - w0);
+        const float e = g.lambda2 * r + g.half_theta * g.lambda1 * (2.f * wn - w0);
+        out[o] = e;
+        vmax = fmaxf(vmax, fabsf(e));
         wD[o] = wn;
         const double rd = (double)r, dw = (double)wn - (double)w0;
         s_abs += fabs(rd);
@@ -213,26 +255,22 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
       }
     }
   }
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+    __shared__ float sm[4];
+    if ((tid & 63) == 0) sm[tid >> 6] = vmax;
+    __syncthreads();
+    if (tid == 0) pmax[bid] = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+  }
   if constexpr (WZD) {
-    __shared__ double red[4 * 3];
     double v[3] = {s_abs, s_sq, s_dw};
-    block_sum<3>(v, red);
-    const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
-    const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum<3>(v);
     if (tid == 0) {
       part[(size_t)bid * 3 + 0] = v[0];
       part[(size_t)bid * 3 + 1] = v[1];
       part[(size_t)bid * 3 + 2] = v[2];
-    }
-    if (last_block(&sc->counters[kCntFwd], nb)) {
-      double a[3];
-      reduce_parts<3>(part, nb, a, red);
-      if (tid == 0) {
-        sc->data_abs = a[0];
-        sc->data_sq = a[1];
-        sc->dwD2 = a[2];
-        sc->counters[kCntFwd] = 0;
-      }
     }
   }
 }
@@ -240,93 +278,215 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
 // ---------------------------------------------------------------------------
 // Adjoint sum_k A_k^T lr_k = sum_k W_k^T B^T D^T lr_k into per-tile partial
 // images [tile][a_ey][a_ex] (HR tile + warp halo).  grid = (a_ntx, a_nty).
+//
+// The scatter W_k^T accumulates in 64-bit fixed point in LDS (ds_add_u64):
+// LDS float atomics run ~30x slower than integer ones on this part, and
+// integer addition is associative, so the sums are also bitwise reproducible.
+// Every contribution c = u * w has |c| <= M = max |lr| (the polyphase taps and
+// the bilinear weights are non-negative and sum to at most 1), so with
+// S = 2^(30 - ceil(log2 M)) each c * S rounds to an int32 without saturation
+// (resolution 2^-30 M per contribution) and at most sk*(2 halo + 1)^2
+// contributions per cell keep the 64-bit sum far from overflow.  M comes from
+// the producer's per-block maxima (`pmax`, npmax of them).
+template <int MMT>  // compile-time bound on the taps per polyphase phase (0: taps read from LDS)
 __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __restrict__ lr,
                                                       const float* __restrict__ disp, float* __restrict__ outp,
+                                                      const float* __restrict__ pmax, int npmax,
                                                       const DevScalars* __restrict__ sc, int gate) {
-  if (gated(sc, gate)) return;
-  extern __shared__ float smem[];
-  const int zeta = g.zeta, rb = g.rb, h = g.halo;
+  if (gated(sc, g, gate)) return;
+  extern __shared__ long long smem8[];  // 8-byte aligned: the accumulator comes first
+  float* smem = reinterpret_cast<float*>(smem8);
+  const int zeta = g.zeta, rb = g.rb, h = g.halo, kb = g.kb;
   const int TH = g.a_th, TW = g.a_tw, EY = g.a_ey, EX = g.a_ex;
-  const int ci = (rb + zeta - 1) / zeta;  // LR rows/cols of blur reach
+  const int ci = (rb + zeta - 1) / zeta;           // LR rows/cols within blur reach
   const int LY = g.a_tly + 2 * ci, LX = g.a_tlx + 2 * ci;
-  float* acc = smem;                // [4][EY][EX] one accumulator per wave
-  float* et = acc + 4 * EY * EX;    // [2][LY][LX] LR tile of the view (double buffered)
-  float* hv = et + 2 * LY * LX;     // [2][TH][LX] vertical B^T pass
+  const int MM = (2 * rb) / zeta + 1;              // max lattice points within +-rb
+  const int PAD = zeta * MM;                       // zero taps below index 0 (indices reach 1 - zeta*MM)
+  const int ETS = (LY + MM) * LX, HVS = TH * LX + MM;
+  long long* acc = smem8;            // [EY][EX] fixed-point accumulator
+  float* et = smem + 2 * EY * EX;    // [2][LY+MM][LX] LR tile (double buffered, zero-padded rows)
+  float* hv = et + 2 * ETS;          // [2][TH*LX + MM] vertical B^T pass
+  float* gs = hv + 2 * HVS;          // [PAD + kb] taps, zeros below
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < EY * EX; idx += kThreads) acc[idx] = 0;
+  for (int idx = tid; idx < 2 * ETS; idx += kThreads) et[idx] = 0.f;
+  for (int idx = tid; idx < 2 * HVS; idx += kThreads) hv[idx] = 0.f;
+  for (int idx = tid; idx < PAD + kb; idx += kThreads) gs[idx] = idx < PAD ? 0.f : g.g[idx - PAD];
+
+  // fixed-point scale from the producer's block maxima (order-free, so exact)
+  float mloc = 0.f;
+  for (int i = tid; i < npmax; i += kThreads) mloc = fmaxf(mloc, pmax[i]);
+  __shared__ float smax[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, off, 64));
+  if ((tid & 63) == 0) smax[tid >> 6] = mloc;
+  __syncthreads();
+  const float M = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+  int eM = 0;
+  if (M > 0.f) (void)frexpf(M, &eM);               // M < 2^eM
+  const int sexp = min(max(30 - eM, -120), 120);
+  const float S = ldexpf(1.f, sexp), invS = ldexpf(1.f, -sexp);
+
   const int ty = blockIdx.y, tx = blockIdx.x;
   const int i0 = ty * g.a_tly, j0 = tx * g.a_tlx;
   const int Y0 = i0 * zeta, X0 = j0 * zeta;
-  const int tid = threadIdx.x, wave = tid >> 6;
-  float* myacc = acc + wave * EY * EX;
-  for (int idx = tid; idx < 4 * EY * EX; idx += kThreads) acc[idx] = 0.f;
+  const int nslot = (TH * TW + kThreads - 1) / kThreads;  // uniform
 
-  float omr[kAdjMaxPix];
+  // LR tile values this thread stages (global offset within a view, -1 = zero)
+  int eoff[kAdjESlots];
 #pragma unroll
-  for (int s = 0; s < kAdjMaxPix; ++s) {
+  for (int s = 0; s < kAdjESlots; ++s) {
     const int idx = tid + s * kThreads;
-    float w = 0.f;
-    if (s < g.a_npix && idx < TH * TW) {
-      const int ly = idx / TW, lx = idx - ly * TW;
-      const int Y = Y0 + ly, X = X0 + lx;
-      if (Y < g.H && X < g.W) w = disp[(size_t)Y * g.W + X];
-    }
-    omr[s] = w;
+    const int a = idx / LX, b = idx - a * LX;
+    const int i = i0 - ci + a, j = j0 - ci + b;
+    eoff[s] = (idx < LY * LX && i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? i * g.sx + j : -1;
   }
-  const float hmin = (float)(-h), hmax = (float)(h - 1);
+  // vertical-pass outputs (ly, b): LR rows i = Y div zeta + m, m in [m_lo, m_lo + MM),
+  // tap Y - zeta i + rb (zero beyond the kernel)
+  int vbase[kAdjVSlots], vtap[kAdjVSlots];
+#pragma unroll
+  for (int s = 0; s < kAdjVSlots; ++s) {
+    const int idx = tid + s * kThreads;
+    const int ly = idx / LX, b = idx - ly * LX;
+    const int ph = ly % zeta, lq = ly / zeta;
+    const int mlo = floordiv(ph - rb + zeta - 1, zeta);
+    vbase[s] = idx < TH * LX ? (lq + mlo + ci) * LX + b : 0;
+    vtap[s] = PAD + ph - zeta * mlo + rb;
+  }
+  // scatter pixels: disparity (clamped), horizontal-pass base/tap, accumulator base
+  float om[kAdjSlots];
+  int hbase[kAdjSlots], htap[kAdjSlots], abase[kAdjSlots];
+  bool act[kAdjSlots];
+#pragma unroll
+  for (int s = 0; s < kAdjSlots; ++s) {
+    const int idx = tid + s * kThreads;
+    const int ly = idx / TW, lx = idx - ly * TW;
+    const int Y = Y0 + ly, X = X0 + lx;
+    act[s] = idx < TH * TW && Y < g.H && X < g.W;
+    om[s] = act[s] ? fminf(fmaxf(disp[(size_t)Y * g.W + X], -g.disp_bound), g.disp_bound) : 0.f;
+    const int ph = lx % zeta, lq = lx / zeta;
+    const int mlo = floordiv(ph - rb + zeta - 1, zeta);
+    hbase[s] = act[s] ? ly * LX + lq + mlo + ci : 0;
+    htap[s] = PAD + ph - zeta * mlo + rb;
+    abase[s] = (ly + h) * EX + (lx + h);
+  }
+  float ereg[kAdjESlots];
+#pragma unroll
+  for (int s = 0; s < kAdjESlots; ++s) ereg[s] = eoff[s] >= 0 ? lr[eoff[s]] : 0.f;
+  __syncthreads();  // gs ready
+  // polyphase taps in registers; the horizontal ones carry the fixed-point scale S
+  constexpr int RT = MMT > 0 ? MMT : 1;
+  float vt[kAdjVSlots][RT], ht[kAdjSlots][RT];
+  if constexpr (MMT > 0) {
+#pragma unroll
+    for (int s = 0; s < kAdjVSlots; ++s)
+#pragma unroll
+      for (int m = 0; m < MMT; ++m) vt[s][m] = m < MM ? gs[vtap[s] - zeta * m] : 0.f;
+#pragma unroll
+    for (int s = 0; s < kAdjSlots; ++s)
+#pragma unroll
+      for (int m = 0; m < MMT; ++m) ht[s][m] = m < MM ? gs[htap[s] - zeta * m] * S : 0.f;
+  }
 
+  unsigned long long* accu = reinterpret_cast<unsigned long long*>(acc);
+  // truncation to int32 (|c| <= 2^30 by the choice of S), sign-extended to 64 bits
+  auto add_fixed = [&](int cell, float c) { atomicAdd(accu + cell, (unsigned long long)(long long)(int)c); };
+
+  int rowoff[kAdjSlots];
+  float wy0[kAdjSlots], wy1[kAdjSlots];
   for (int k = 0; k < g.sk; ++k) {
     const int buf = k & 1;
-    float* e_ = et + buf * LY * LX;
-    float* h_ = hv + buf * TH * LX;
-    const float* lk = lr + (size_t)k * g.q;
-    for (int idx = tid; idx < LY * LX; idx += kThreads) {
-      const int a = idx / LX, b = idx - a * LX;
-      const int i = i0 - ci + a, j = j0 - ci + b;
-      e_[idx] = (i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? lk[(size_t)i * g.sx + j] : 0.f;
-    }
-    __syncthreads();
-    // B^T D^T, vertical: every LR sample i with |Y - zeta i| <= rb feeds row Y
-    for (int idx = tid; idx < TH * LX; idx += kThreads) {
-      const int ly = idx / LX, b = idx - ly * LX;
-      const int Y = Y0 + ly;
-      const int ilo = floordiv(Y - rb + zeta - 1, zeta), ihi = floordiv(Y + rb, zeta);
-      float a_ = 0.f;
-      for (int i = ilo; i <= ihi; ++i) a_ = fmaf(g.g[Y - zeta * i + rb], e_[(i - i0 + ci) * LX + b], a_);
-      h_[idx] = a_;
-    }
-    __syncthreads();
-    const float tau = (float)(k / g.V - (g.U - 1) / 2);
-    const float rho = (float)(k % g.V - (g.V - 1) / 2);
+    float* e_ = et + buf * ETS;
+    float* h_ = hv + buf * HVS;
 #pragma unroll
-    for (int s = 0; s < kAdjMaxPix; ++s) {
+    for (int s = 0; s < kAdjESlots; ++s) {
       const int idx = tid + s * kThreads;
-      if (s >= g.a_npix || idx >= TH * TW) break;
-      const int ly = idx / TW, lx = idx - ly * TW;
-      const int Y = Y0 + ly, X = X0 + lx;
-      if (Y >= g.H || X >= g.W) continue;
-      // B^T D^T, horizontal
-      const int jlo = floordiv(X - rb + zeta - 1, zeta), jhi = floordiv(X + rb, zeta);
+      if (idx < LY * LX) e_[idx] = ereg[s];
+    }
+    if (k + 1 < g.sk) {  // prefetch the next view's LR tile
+      const float* ln = lr + (size_t)(k + 1) * g.q;
+#pragma unroll
+      for (int s = 0; s < kAdjESlots; ++s) ereg[s] = eoff[s] >= 0 ? ln[eoff[s]] : 0.f;
+    }
+    // the vertical warp coordinate is shared by the views of an angular row
+    const int ka = k / g.V, kbcol = k - ka * g.V;
+    if (kbcol == 0) {
+      const float tau = (float)(ka - (g.U - 1) / 2);
+#pragma unroll
+      for (int s = 0; s < kAdjSlots; ++s) {
+        const float sy = tau * om[s];
+        const float fy0 = floorf(sy);
+        wy1[s] = sy - fy0;
+        wy0[s] = 1.f - wy1[s];
+        rowoff[s] = (int)fy0 * EX;
+      }
+    }
+    __syncthreads();
+    // B^T D^T, vertical
+    float vv[kAdjVSlots];
+#pragma unroll
+    for (int s = 0; s < kAdjVSlots; ++s) vv[s] = 0.f;
+    if constexpr (MMT > 0) {
+#pragma unroll
+      for (int m = 0; m < MMT; ++m) {
+        if (m < MM) {
+#pragma unroll
+          for (int s = 0; s < kAdjVSlots; ++s) vv[s] = fmaf(vt[s][m], e_[vbase[s] + m * LX], vv[s]);
+        }
+      }
+    } else {
+      for (int m = 0; m < MM; ++m) {
+#pragma unroll
+        for (int s = 0; s < kAdjVSlots; ++s) vv[s] = fmaf(gs[vtap[s] - zeta * m], e_[vbase[s] + m * LX], vv[s]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kAdjVSlots; ++s) {
+      const int idx = tid + s * kThreads;
+      if (idx < TH * LX) h_[idx] = vv[s];
+    }
+    __syncthreads();
+    // B^T D^T, horizontal (scaled by S); then W_k^T: send u back to the four taps W_k read
+    const float rho = (float)(kbcol - (g.V - 1) / 2);
+#pragma unroll
+    for (int s = 0; s < kAdjSlots; ++s) {
+      if (s >= nslot) break;
       float u = 0.f;
-      for (int j = jlo; j <= jhi; ++j) u = fmaf(g.g[X - zeta * j + rb], h_[ly * LX + (j - j0 + ci)], u);
-      // W_k^T: send u back to the four taps W_k read it from
-      const float w = omr[s];
-      const float sy = tau * w, sx = rho * w;
-      float fy0 = floorf(sy), fx0 = floorf(sx);
-      const float fy = sy - fy0, fx = sx - fx0;
-      fy0 = fminf(fmaxf(fy0, hmin), hmax);
-      fx0 = fminf(fmaxf(fx0, hmin), hmax);
-      float* a = myacc + (ly + h + (int)fy0) * EX + (lx + h + (int)fx0);
-      const float u0 = u * (1.f - fy), u1 = u * fy;
-      atomicAdd(a, u0 * (1.f - fx));
-      atomicAdd(a + 1, u0 * fx);
-      atomicAdd(a + EX, u1 * (1.f - fx));
-      atomicAdd(a + EX + 1, u1 * fx);
+      if constexpr (MMT > 0) {
+#pragma unroll
+        for (int m = 0; m < MMT; ++m)
+          if (m < MM) u = fmaf(ht[s][m], h_[hbase[s] + m], u);
+      } else {
+        for (int m = 0; m < MM; ++m) u = fmaf(gs[htap[s] - zeta * m] * S, h_[hbase[s] + m], u);
+      }
+      if (!act[s]) continue;
+      const float sx = rho * om[s];
+      const float fx0 = floorf(sx);
+      const float fx = sx - fx0, gx = 1.f - fx;
+      const int cell = abase[s] + rowoff[s] + (int)fx0;
+      const float u0 = u * wy0[s], u1 = u * wy1[s];
+      add_fixed(cell, u0 * gx);
+      add_fixed(cell + 1, u0 * fx);
+      add_fixed(cell + EX, u1 * gx);
+      add_fixed(cell + EX + 1, u1 * fx);
     }
   }
   __syncthreads();
   float* o = outp + ((size_t)ty * g.a_ntx + tx) * (size_t)(EY * EX);
-  const int n = EY * EX;
-  for (int idx = tid; idx < n; idx += kThreads)
-    o[idx] = ((acc[idx] + acc[n + idx]) + acc[2 * n + idx]) + acc[3 * n + idx];
+  for (int idx = tid; idx < EY * EX; idx += kThreads) o[idx] = (float)acc[idx] * invS;
+}
+
+// Per-block max |v| of n floats (scale input of the adjoint entry point).
+__global__ __launch_bounds__(kThreads) void k_absmax(const float* __restrict__ v, long long n, float* __restrict__ pmax) {
+  float m = 0.f;
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads)
+    m = fmaxf(m, fabsf(v[o]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  __shared__ float sm[4];
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) pmax[blockIdx.x] = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
 }
 
 // out = sum of the adjoint partial images (the operator entry point).
@@ -342,12 +502,85 @@ __global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restr
 //   g_d = c_d m (x - S_d x)  (dropped where z+d is outside),
 //   w_S' = clip(g_d + w_S, +-1/vartheta),  f_d = 2 w_S' - w_S,
 //   vs = S^T f = sum_d [c_d m(z) f_d(z) 1(z+d in) - c_d m(z-d) f_d(z-d) 1(z-d in)].
-// The second term is pulled, recomputing f_d(z-d) from the previous dual
-// (ping-pong buffers make that read race-free).  grid = (ceil(W/64), ceil(H/16)).
+// The second term is pulled: f_d(z-d) is recomputed from the previous dual,
+// which ping-pong buffers keep intact.  Per-block partials {sum|g|,
+// sum (w_S'-w_S)^2} go to `part`.  grid = (ceil(W/64), ceil(H/16)).
+template <bool INTERIOR>
+__device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__ xs, const float* __restrict__ ms,
+                                        const float* wo, float* wn_, float* __restrict__ vs, int X0, int Y0,
+                                        double& s_abs, double& s_dw) {
+  const int rw = g.rw;
+  const int LXd = kTvTileX + 2 * rw;
+  const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
+  const int X = X0 + lx;
+  int Y[4], sl[4];
+  bool in[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int ly = ly0 + 4 * rr;
+    Y[rr] = Y0 + ly;
+    in[rr] = INTERIOR || (Y[rr] < g.H && X < g.W);
+    sl[rr] = (ly + rw) * LXd + (lx + rw);
+  }
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  // software pipeline: the dual values of offsets d+1 and d+2 are in flight while d is used
+  float c0[4], c2[4], n0[4], n2[4];
+  auto load = [&](int d, float (&w0)[4], float (&w2)[4]) {
+    const int dy = g.ody[d], dx = g.odx[d];
+    const float* wd = wo + (size_t)d * g.p;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const size_t o = (size_t)Y[rr] * g.W + X;
+      w0[rr] = in[rr] ? wd[o] : 0.f;
+      const bool bin = INTERIOR || (in[rr] && Y[rr] - dy >= 0 && Y[rr] - dy < g.H && X - dx >= 0 && X - dx < g.W);
+      w2[rr] = bin ? wd[o - (ptrdiff_t)dy * g.W - dx] : 0.f;
+    }
+  };
+  if (g.sd > 0) load(0, c0, c2);
+  if (g.sd > 1) load(1, n0, n2);
+  for (int d = 0; d < g.sd; ++d) {
+    float w0[4], w2[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      w0[rr] = c0[rr];
+      w2[rr] = c2[rr];
+      c0[rr] = n0[rr];
+      c2[rr] = n2[rr];
+    }
+    if (d + 2 < g.sd) load(d + 2, n0, n2);
+    const int dy = g.ody[d], dx = g.odx[d];
+    const int dd = dy * LXd + dx;
+    const float c = g.cd[d];
+    float* wnd = wn_ + (size_t)d * g.p;
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      if (!in[rr]) continue;
+      const float xz = xs[sl[rr]], mz = ms[sl[rr]];
+      const bool fin = INTERIOR || (Y[rr] + dy >= 0 && Y[rr] + dy < g.H && X + dx >= 0 && X + dx < g.W);
+      const float gv = fin ? c * mz * (xz - xs[sl[rr] + dd]) : 0.f;
+      const float wn = clipf(gv + w0[rr], g.clip);
+      wnd[(size_t)Y[rr] * g.W + X] = wn;
+      if (fin) acc[rr] = fmaf(c * mz, 2.f * wn - w0[rr], acc[rr]);
+      const double dw = (double)wn - (double)w0[rr];
+      s_abs += fabs((double)gv);
+      s_dw += dw * dw;
+      const bool bin = INTERIOR || (Y[rr] - dy >= 0 && Y[rr] - dy < g.H && X - dx >= 0 && X - dx < g.W);
+      if (bin) {
+        const float mm = ms[sl[rr] - dd];
+        const float g2 = c * mm * (xs[sl[rr] - dd] - xz);
+        const float wn2 = clipf(g2 + w2[rr], g.clip);
+        acc[rr] = fmaf(-(c * mm), 2.f * wn2 - w2[rr], acc[rr]);
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+    if (in[rr]) vs[(size_t)Y[rr] * g.W + X] = acc[rr];
+}
+
 __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict__ x, const float* __restrict__ m,
-                                                 float* __restrict__ ws0, float* __restrict__ ws1,
-                                                 float* __restrict__ vs, double* __restrict__ part,
-                                                 DevScalars* __restrict__ sc) {
+                                                 float* ws0, float* ws1, float* __restrict__ vs,
+                                                 double* __restrict__ part, const DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
   extern __shared__ float smem[];
   const int rw = g.rw;
@@ -355,8 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict
   float* xs = smem;
   float* ms = xs + LYd * LXd;
   const int X0 = blockIdx.x * kTvTileX, Y0 = blockIdx.y * kTvTileY;
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < LYd * LXd; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < LYd * LXd; idx += kThreads) {
     const int a = idx / LXd, b = idx - a * LXd;
     const int Y = Y0 - rw + a, X = X0 - rw + b;
     const bool in = Y >= 0 && Y < g.H && X >= 0 && X < g.W;
@@ -366,66 +598,16 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict
   __syncthreads();
   const float* wo = sc->wcur ? ws1 : ws0;
   float* wn_ = sc->wcur ? ws0 : ws1;
-  const int lx = tid & 63, ly0 = tid >> 6;
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const bool interior = X0 - rw >= 0 && X0 + kTvTileX + rw <= g.W && Y0 - rw >= 0 && Y0 + kTvTileY + rw <= g.H;
   double s_abs = 0.0, s_dw = 0.0;
-  const int half = (g.win * g.win) / 2;
-  for (int d = 0; d < g.sd; ++d) {
-    const int id = d < half ? d : d + 1;
-    const int dy = id / g.win - rw, dx = id - (id / g.win) * g.win - rw;
-    const float c = g.cd[d];
-    const float* wod = wo + (size_t)d * g.p;
-    float* wnd = wn_ + (size_t)d * g.p;
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int ly = ly0 + 4 * rr;
-      const int Y = Y0 + ly, X = X0 + lx;
-      if (Y >= g.H || X >= g.W) continue;
-      const size_t o = (size_t)Y * g.W + X;
-      const int sl = (ly + rw) * LXd + (lx + rw);
-      const float xz = xs[sl], mz = ms[sl];
-      const bool fwd_in = Y + dy >= 0 && Y + dy < g.H && X + dx >= 0 && X + dx < g.W;
-      const float gv = fwd_in ? c * mz * (xz - xs[sl + dy * LXd + dx]) : 0.f;
-      const float w0 = wod[o];
-      const float wn = clipf(gv + w0, g.clip);
-      wnd[o] = wn;
-      if (fwd_in) acc[rr] = fmaf(c * mz, 2.f * wn - w0, acc[rr]);
-      const double dw = (double)wn - (double)w0;
-      s_abs += fabs((double)gv);
-      s_dw += dw * dw;
-      const int Ym = Y - dy, Xm = X - dx;
-      if (Ym >= 0 && Ym < g.H && Xm >= 0 && Xm < g.W) {
-        const int sm = sl - dy * LXd - dx;
-        const float mm = ms[sm];
-        const float g2 = c * mm * (xs[sm] - xz);
-        const float w2 = wod[(size_t)Ym * g.W + Xm];
-        const float wn2 = clipf(g2 + w2, g.clip);
-        acc[rr] = fmaf(-(c * mm), 2.f * wn2 - w2, acc[rr]);
-      }
-    }
-  }
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int Y = Y0 + ly0 + 4 * rr, X = X0 + lx;
-    if (Y < g.H && X < g.W) vs[(size_t)Y * g.W + X] = acc[rr];
-  }
-  __shared__ double red[4 * 2];
+  if (interior) tv_tile<true>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  else tv_tile<false>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
   double v[2] = {s_abs, s_dw};
-  block_sum<2>(v, red);
-  const unsigned nb = gridDim.x * gridDim.y;
-  const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
-  if (tid == 0) {
+  block_sum<2>(v);
+  if (threadIdx.x == 0) {
+    const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
     part[(size_t)bid * 2 + 0] = v[0];
     part[(size_t)bid * 2 + 1] = v[1];
-  }
-  if (last_block(&sc->counters[kCntTv], nb)) {
-    double a[2];
-    reduce_parts<2>(part, nb, a, red);
-    if (tid == 0) {
-      sc->reg_abs = a[0];
-      sc->dwS2 = a[1];
-      sc->counters[kCntTv] = 0;
-    }
   }
 }
 
@@ -434,12 +616,28 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict
 // part written as the symmetric weighted Laplacian
 //   sum_d c_d^2 (m(z)^2 + m(z+d)^2) (p(z) - p(z+d)) 1(z+d in the image),
 // which equals S^T V^2 S p because the offset set is symmetric.  With
-// with_dot, also <p, Hp> and alpha = pi / <p, Hp> (last block).
+// with_dot, per-block partials of <p, Hp> go to `part`.
+template <bool INTERIOR>
+__device__ __forceinline__ float tv_laplacian(const Geom& g, const float* __restrict__ ps,
+                                              const float* __restrict__ m2, int sl, int Y, int X, int LXd) {
+  const float pz = ps[sl], mz = m2[sl];
+  float lap = 0.f;
+#pragma unroll 8
+  for (int d = 0; d < g.sd; ++d) {
+    const int dy = g.ody[d], dx = g.odx[d];
+    const int sn = sl + dy * LXd + dx;
+    float t = g.cd2[d] * (mz + m2[sn]) * (pz - ps[sn]);
+    if (!INTERIOR && (Y + dy < 0 || Y + dy >= g.H || X + dx < 0 || X + dx >= g.W)) t = 0.f;
+    lap += t;
+  }
+  return lap;
+}
+
 __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict__ pv, const float* __restrict__ m,
                                                  const float* __restrict__ adj, float* __restrict__ hp,
-                                                 double* __restrict__ part, DevScalars* __restrict__ sc, int gate,
-                                                 int with_dot) {
-  if (gated(sc, gate)) return;
+                                                 double* __restrict__ part, const DevScalars* __restrict__ sc,
+                                                 int gate, int with_dot) {
+  if (gated(sc, g, gate)) return;
   extern __shared__ float smem[];
   const int rw = g.rw;
   const int LXd = kTvTileX + 2 * rw, LYd = kTvTileY + 2 * rw;
@@ -458,8 +656,8 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
     }
   }
   __syncthreads();
+  const bool interior = X0 - rw >= 0 && X0 + kTvTileX + rw <= g.W && Y0 - rw >= 0 && Y0 + kTvTileY + rw <= g.H;
   const int lx = tid & 63, ly0 = tid >> 6;
-  const int half = (g.win * g.win) / 2;
   double s_dot = 0.0;
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
@@ -470,141 +668,177 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
     float lap = 0.f;
     if (g.sd > 0) {
       const int sl = (ly + rw) * LXd + (lx + rw);
-      const float pz = ps[sl], mz = m2[sl];
-      for (int d = 0; d < g.sd; ++d) {
-        const int id = d < half ? d : d + 1;
-        const int dy = id / g.win - rw, dx = id - (id / g.win) * g.win - rw;
-        if (Y + dy < 0 || Y + dy >= g.H || X + dx < 0 || X + dx >= g.W) continue;
-        const int sn = sl + dy * LXd + dx;
-        lap = fmaf(g.cd2[d] * (mz + m2[sn]), pz - ps[sn], lap);
-      }
+      lap = interior ? tv_laplacian<true>(g, ps, m2, sl, Y, X, LXd) : tv_laplacian<false>(g, ps, m2, sl, Y, X, LXd);
     }
     const float v = g.cA * adj_merge(g, adj, Y, X) + g.half_theta * lap;
     hp[o] = v;
     if (with_dot) s_dot += (double)pv[o] * (double)v;
   }
   if (!with_dot) return;
-  __shared__ double red[4];
   double v[1] = {s_dot};
-  block_sum<1>(v, red);
-  const unsigned nb = gridDim.x * gridDim.y;
-  const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
-  if (tid == 0) part[bid] = v[0];
-  if (last_block(&sc->counters[kCntHp], nb)) {
-    double a[1];
-    reduce_parts<1>(part, nb, a, red);
-    if (tid == 0) {
-      const double php = a[0];
-      sc->php = php;
-      if (php > 0.0) {
-        sc->alpha = sc->pi / php;
-      } else {
-        sc->alpha = 0.0;
-        sc->cg_done = 1;
-      }
-      sc->counters[kCntHp] = 0;
-    }
-  }
+  block_sum<1>(v);
+  if (tid == 0) part[blockIdx.x + gridDim.x * blockIdx.y] = v[0];
 }
 
 // ---------------------------------------------------------------------------
 // CG start (Algorithm 2 from delta = 0): v = A^T e + (vartheta/2) S^T f,
-// r = -v, p = r, pi = <r, r>.  The last block also closes the wz-step's
-// statistics: J(x^(n-1)) and the primal residual.
+// r = -v, p = r, partials of <r, r>.  Block 0 also closes the wz-step's
+// statistics: J(x^(n-1)), the primal residual and the stop test.
 __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __restrict__ adj,
                                                      const float* __restrict__ vs, float* __restrict__ r,
-                                                     float* __restrict__ pv, double* __restrict__ part,
-                                                     DevScalars* __restrict__ sc, double* __restrict__ stats_row) {
+                                                     float* __restrict__ pv, double* __restrict__ prr,
+                                                     const double* __restrict__ pwzd, int nwzd,
+                                                     const double* __restrict__ ptv, int ntv,
+                                                     double* __restrict__ stats, DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
   double s = 0.0;
-  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
-    const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
-    float v = adj_merge(g, adj, Y, X);
-    if (g.sd > 0) v += g.half_theta * vs[o];
-    const float rv = -v;
-    r[o] = rv;
-    pv[o] = rv;
-    s += (double)rv * (double)rv;
-  }
-  __shared__ double red[4];
-  double v[1] = {s};
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-  if (last_block(&sc->counters[kCntInit], gridDim.x)) {
-    double a[1];
-    reduce_parts<1>(part, gridDim.x, a, red);
-    if (threadIdx.x == 0) {
-      const double pi = a[0];
-      sc->pi = pi;
-      sc->cg_steps = 0;
-      sc->cg_done = (!(pi > (double)g.cg_tol) || pi == 0.0) ? 1 : 0;
-      const double reg = g.sd > 0 ? sc->reg_abs : 0.0;
-      const double dws = g.sd > 0 ? sc->dwS2 : 0.0;
-      const double data = (double)g.lambda1 * sc->data_abs + (double)g.lambda2 * sc->data_sq;
-      const double res = sqrt(sc->dwD2 + dws);
-      stats_row[0] = data + reg;
-      stats_row[1] = res;
-      stats_row[4] = data;
-      stats_row[5] = reg;
-      if (!sc->res1_set) {
-        sc->res1 = res;
-        sc->res1_set = 1;
+  const long long gstride = (long long)gridDim.x * kThreads * 4;
+  for (long long o0 = blockIdx.x * (long long)kThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long o = o0 + j * kThreads;
+      v[j] = 0.f;
+      if (o < g.p) {
+        const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
+        v[j] = adj_merge(g, adj, Y, X);
+        if (g.sd > 0) v[j] += g.half_theta * vs[o];
       }
-      if (g.stop_tol > 0.f && res <= (double)g.stop_tol * sc->res1) sc->stop_pending = 1;
-      sc->counters[kCntInit] = 0;
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long o = o0 + j * kThreads;
+      if (o < g.p) {
+        const float rv = -v[j];
+        r[o] = rv;
+        pv[o] = rv;
+        s += (double)rv * (double)rv;
+      }
+    }
+  }
+  double v[1] = {s};
+  block_sum<1>(v);
+  if (threadIdx.x == 0) prr[blockIdx.x] = v[0];
+  if (blockIdx.x != 0) return;
+  double a[3], b[2] = {0.0, 0.0};
+  sum_parts<3>(pwzd, nwzd, a);
+  if (g.sd > 0) sum_parts<2>(ptv, ntv, b);
+  if (threadIdx.x == 0) {
+    double* row = stats_row(g, stats, sc);
+    const double data = (double)g.lambda1 * a[0] + (double)g.lambda2 * a[1];
+    const double res = sqrt(a[2] + b[1]);
+    row[0] = data + b[0];
+    row[1] = res;
+    row[4] = data;
+    row[5] = b[0];
+    if (!sc->res1_set) {
+      sc->res1 = res;
+      sc->res1_set = 1;
+    }
+    if (g.stop_tol > 0.f && res <= (double)g.stop_tol * sc->res1) sc->stop_pending = 1;
+    sc->cg_done = 0;
+    sc->cg_steps = 0;
   }
 }
 
-// x += alpha p (the x-step accumulates straight into x), r -= alpha Hp,
-// pi' = <r, r>, beta = pi'/pi; CG stops once pi' <= tau or pi' = 0.
+// CG step `step` (1-based), part 1: pi = <r,r> from the previous partials,
+// alpha = pi / <p, Hp>; x += alpha p (the x-step accumulates straight into x),
+// r -= alpha Hp, partials of the new <r, r>.  CG stops (Algorithm 2) when
+// pi <= tau, pi = 0, or <p, Hp> <= 0.
 __global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ x, float* __restrict__ r,
                                                     const float* __restrict__ pv, const float* __restrict__ hp,
-                                                    double* __restrict__ part, DevScalars* __restrict__ sc) {
+                                                    const double* __restrict__ prr_prev, double* __restrict__ prr_new,
+                                                    const double* __restrict__ pphp, int nphp, int step,
+                                                    DevScalars* __restrict__ sc) {
   if (sc->admm_done || sc->cg_done) return;
-  const float alpha = (float)sc->alpha;
-  double s = 0.0;
-  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
-    x[o] = fmaf(alpha, pv[o], x[o]);
-    const float rv = fmaf(-alpha, hp[o], r[o]);
-    r[o] = rv;
-    s += (double)rv * (double)rv;
+  double t[2];
+  {
+    double a[1], b[1];
+    sum_parts<1>(prr_prev, g.red_blocks, a);
+    sum_parts<1>(pphp, nphp, b);
+    t[0] = a[0];
+    t[1] = b[0];
   }
-  __shared__ double red[4];
+  const double pi = t[0], php = t[1];
+  if (!(pi > (double)g.cg_tol) || pi == 0.0 || !(php > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->cg_done = 1;
+    return;
+  }
+  const float alpha = (float)(pi / php);
+  double s = 0.0;
+  const long long gstride = (long long)gridDim.x * kThreads * 4;
+  for (long long o0 = blockIdx.x * (long long)kThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
+    float xv[4], pw[4], hw[4], rw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long o = o0 + j * kThreads;
+      const bool in = o < g.p;
+      xv[j] = in ? x[o] : 0.f;
+      pw[j] = in ? pv[o] : 0.f;
+      hw[j] = in ? hp[o] : 0.f;
+      rw[j] = in ? r[o] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long o = o0 + j * kThreads;
+      if (o < g.p) {
+        x[o] = fmaf(alpha, pw[j], xv[j]);
+        const float rv = fmaf(-alpha, hw[j], rw[j]);
+        r[o] = rv;
+        s += (double)rv * (double)rv;
+      }
+    }
+  }
   double v[1] = {s};
-  block_sum<1>(v, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
-  if (last_block(&sc->counters[kCntUpd], gridDim.x)) {
-    double a[1];
-    reduce_parts<1>(part, gridDim.x, a, red);
-    if (threadIdx.x == 0) {
-      const double pin = a[0];
-      sc->beta = pin / sc->pi;
-      sc->pi = pin;
-      sc->cg_steps += 1;
-      if (!(pin > (double)g.cg_tol) || pin == 0.0) sc->cg_done = 1;
-      sc->counters[kCntUpd] = 0;
+  block_sum<1>(v);
+  if (threadIdx.x == 0) prr_new[blockIdx.x] = v[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->cg_steps = step;
+}
+
+// CG step part 2: beta = pi_new / pi_old, p = r + beta p.
+__global__ __launch_bounds__(kThreads) void k_cgp(Geom g, const float* __restrict__ r, float* __restrict__ pv,
+                                                  const double* __restrict__ prr_old,
+                                                  const double* __restrict__ prr_new,
+                                                  const DevScalars* __restrict__ sc) {
+  if (sc->admm_done || sc->cg_done) return;
+  double a[1], b[1];
+  sum_parts<1>(prr_new, g.red_blocks, a);
+  sum_parts<1>(prr_old, g.red_blocks, b);
+  const float beta = (float)(a[0] / b[0]);
+  const long long gstride = (long long)gridDim.x * kThreads * 4;
+  for (long long o0 = blockIdx.x * (long long)kThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
+    float pw[4], rw[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long o = o0 + j * kThreads;
+      const bool in = o < g.p;
+      pw[j] = in ? pv[o] : 0.f;
+      rw[j] = in ? r[o] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long o = o0 + j * kThreads;
+      if (o < g.p) pv[o] = fmaf(beta, pw[j], rw[j]);
     }
   }
 }
 
-// p = r + beta p
-__global__ __launch_bounds__(kThreads) void k_cgp(Geom g, const float* __restrict__ r, float* __restrict__ pv,
-                                                  const DevScalars* __restrict__ sc) {
-  if (sc->admm_done || sc->cg_done) return;
-  const float beta = (float)sc->beta;
-  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads)
-    pv[o] = fmaf(beta, pv[o], r[o]);
-}
-
-// End of an ADMM iteration: CG statistics, iteration count, dual ping-pong, stop flag.
-__global__ void k_iter_end(DevScalars* __restrict__ sc, double* __restrict__ stats_row, int has_tv) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// End of an ADMM iteration: final CG pi and step count, iteration count,
+// NLTV-dual ping-pong, stop flag.  One block.
+__global__ __launch_bounds__(kThreads) void k_iter_end(Geom g, const double* __restrict__ prr0,
+                                                       const double* __restrict__ prr1, double* __restrict__ stats,
+                                                       DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
-  stats_row[2] = sc->pi;
-  stats_row[3] = (double)sc->cg_steps;
+  const int steps = sc->cg_steps;
+  double a[1];
+  sum_parts<1>((steps & 1) ? prr1 : prr0, g.red_blocks, a);
+  if (threadIdx.x != 0) return;
+  double* row = stats_row(g, stats, sc);
+  row[2] = a[0];
+  row[3] = (double)steps;
+  sc->pi = a[0];
   sc->iters_done += 1;
-  if (has_tv) sc->wcur ^= 1;
+  if (g.sd > 0) sc->wcur ^= 1;
   if (sc->stop_pending) sc->admm_done = 1;
 }
 
@@ -612,7 +846,7 @@ __global__ void k_iter_end(DevScalars* __restrict__ sc, double* __restrict__ sta
 // sec 3.4: m = exp(-|grad x|^2 / sigma_e) * occ, forward differences.
 __global__ __launch_bounds__(kThreads) void k_edge(Geom g, const float* __restrict__ x, const float* __restrict__ occ,
                                                    float* __restrict__ m, const DevScalars* __restrict__ sc, int gate) {
-  if (gated(sc, gate)) return;
+  if (gated(sc, g, gate)) return;
   for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
     const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
     float we = 1.f;
@@ -682,8 +916,8 @@ __global__ __launch_bounds__(kThreads) void k_check(Geom g, const float* __restr
   if (f) atomicOr(&sc->err_flags, f);
 }
 
-// Fill n floats with a value (used instead of hipMemsetAsync so that the
-// sequence can be captured in a graph).
+// Fill n floats with a value (a kernel rather than hipMemsetAsync, so that
+// the sequence stays capturable in a graph).
 __global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ p, long long n, float v) {
   for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads) p[o] = v;
 }
@@ -691,18 +925,19 @@ __global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ p, long l
 // Reset the device scalars for a fresh state (iters_done = n_done).
 __global__ void k_reset(DevScalars* sc, int n_done) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  sc->pi = sc->alpha = sc->beta = sc->php = 0.0;
-  sc->data_abs = sc->data_sq = sc->dwD2 = sc->reg_abs = sc->dwS2 = 0.0;
+  sc->pi = 0.0;
   sc->res1 = 0.0;
   sc->res1_set = 0;
-  sc->cg_done = sc->admm_done = sc->stop_pending = sc->cg_steps = 0;
+  sc->wcur = 0;
+  sc->cg_done = 0;
+  sc->cg_steps = 0;
+  sc->admm_done = 0;
+  sc->stop_pending = 0;
   sc->iters_done = n_done;
   sc->err_flags = 0;
-  sc->wcur = 0;
-  for (int i = 0; i < 16; ++i) sc->counters[i] = 0;
 }
 
-// Copy the current NLTV dual (selected on the device) out, or a new one in.
+// Copy the current NLTV dual (selected on the device) out.
 __global__ __launch_bounds__(kThreads) void k_copy_ws(const float* __restrict__ ws0, const float* __restrict__ ws1,
                                                       float* __restrict__ out, long long n,
                                                       const DevScalars* __restrict__ sc) {
@@ -713,24 +948,53 @@ __global__ __launch_bounds__(kThreads) void k_copy_ws(const float* __restrict__ 
 // ---------------------------------------------------------------------------
 // Launch helpers (host side).
 
-static inline unsigned grid1d(long long n) {
+static inline unsigned grid1d(long long n, long long cap = 4096) {
   long long b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
-  if (b > kRedBlocks) b = kRedBlocks;
+  if (b > cap) b = cap;
   return (unsigned)b;
 }
 
+static inline void fwd_dims(const Geom& g, int& NY, int& NX, int& SY, int& SX) {
+  NY = (g.f_tly - 1) * g.zeta + 1 + 2 * g.rb;
+  NX = (g.f_tlx - 1) * g.zeta + 1 + 2 * g.rb;
+  SY = NY + 2 * g.halo;
+  SX = NX + 2 * g.halo;
+}
+
 size_t forward_lds(const Geom& g) {
-  const int NY = (g.f_tly - 1) * g.zeta + 1 + 2 * g.rb;
-  const int NX = (g.f_tlx - 1) * g.zeta + 1 + 2 * g.rb;
-  const int SY = NY + 2 * g.halo, SX = NX + 2 * g.halo;
-  return sizeof(float) * ((size_t)SY * SX + 2 * (size_t)NY * NX + (size_t)NY * g.f_tlx);
+  int NY, NX, SY, SX;
+  fwd_dims(g, NY, NX, SY, SX);
+  return sizeof(float) * ((size_t)SY * SX + (size_t)NY * NX + (size_t)NY * g.f_tlx);
+}
+
+bool forward_tile_ok(const Geom& g) {
+  int NY, NX, SY, SX;
+  fwd_dims(g, NY, NX, SY, SX);
+  return NY * NX <= kThreads * kFwdSlots && NY * g.f_tlx <= kThreads * kFwdHSlots &&
+         g.f_tly * g.f_tlx <= kThreads && forward_lds(g) <= 60 * 1024;
+}
+
+static inline void adj_dims(const Geom& g, int& ci, int& LY, int& LX, int& MM, int& PAD) {
+  ci = (g.rb + g.zeta - 1) / g.zeta;
+  LY = g.a_tly + 2 * ci;
+  LX = g.a_tlx + 2 * ci;
+  MM = (2 * g.rb) / g.zeta + 1;
+  PAD = g.zeta * MM;
 }
 
 size_t adjoint_lds(const Geom& g) {
-  const int ci = (g.rb + g.zeta - 1) / g.zeta;
-  const int LY = g.a_tly + 2 * ci, LX = g.a_tlx + 2 * ci;
-  return sizeof(float) * (4 * (size_t)g.a_ey * g.a_ex + 2 * (size_t)LY * LX + 2 * (size_t)g.a_th * LX);
+  int ci, LY, LX, MM, PAD;
+  adj_dims(g, ci, LY, LX, MM, PAD);
+  const size_t ets = (size_t)(LY + MM) * LX, hvs = (size_t)g.a_th * LX + MM;
+  return sizeof(float) * (2 * (size_t)g.a_ey * g.a_ex + 2 * ets + 2 * hvs + PAD + g.kb);
+}
+
+bool adjoint_tile_ok(const Geom& g) {
+  int ci, LY, LX, MM, PAD;
+  adj_dims(g, ci, LY, LX, MM, PAD);
+  return g.a_th >= g.halo && g.a_tw >= g.halo && g.a_th * g.a_tw <= kThreads * kAdjSlots &&
+         g.a_th * LX <= kThreads * kAdjVSlots && LY * LX <= kThreads * kAdjESlots && adjoint_lds(g) <= 60 * 1024;
 }
 
 size_t tv_lds(const Geom& g) {
@@ -742,24 +1006,42 @@ dim3 forward_grid(const Geom& g) {
 }
 dim3 adjoint_grid(const Geom& g) { return dim3(g.a_ntx, g.a_nty, 1); }
 dim3 tv_grid(const Geom& g) { return dim3((g.W + kTvTileX - 1) / kTvTileX, (g.H + kTvTileY - 1) / kTvTileY, 1); }
-unsigned red_blocks(const Geom& g) { return grid1d(g.p); }
+
+static inline int nblocks(dim3 d) { return (int)(d.x * d.y * d.z); }
 
 void launch_forward(const Geom& g, const float* src, const float* disp, float* out, hipStream_t s,
                     const Bufs& b, int gate) {
   hipLaunchKernelGGL(k_forward<false>, forward_grid(g), dim3(kThreads), forward_lds(g), s, g, src, disp, out,
-                     (const float*)nullptr, (float*)nullptr, b.part, b.sc, gate);
+                     (const float*)nullptr, (float*)nullptr, (double*)nullptr, b.p_max, (const DevScalars*)b.sc, gate);
 }
 
 void launch_forward_wzd(const Geom& g, const float* src, const float* disp, const float* y, hipStream_t s,
                         const Bufs& b) {
   hipLaunchKernelGGL(k_forward<true>, forward_grid(g), dim3(kThreads), forward_lds(g), s, g, src, disp, b.lr, y,
-                     b.wD, b.part, b.sc, 1);
+                     b.wD, b.p_wzd, b.p_max, (const DevScalars*)b.sc, (int)kGateAdmm);
 }
 
-void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate) {
-  hipLaunchKernelGGL(k_adjoint, adjoint_grid(g), dim3(kThreads), adjoint_lds(g), s, g, lr, disp, b.adj,
-                     (const DevScalars*)b.sc, gate);
+void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate,
+                    int npmax) {
+  const int MM = (2 * g.rb) / g.zeta + 1;
+  const dim3 grid = adjoint_grid(g), blk(kThreads);
+  const size_t lds = adjoint_lds(g);
+  const float* pm = b.p_max;
+  const DevScalars* sc = b.sc;
+  if (MM <= 2) hipLaunchKernelGGL(k_adjoint<2>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
+  else if (MM <= 3) hipLaunchKernelGGL(k_adjoint<3>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
+  else if (MM <= 4) hipLaunchKernelGGL(k_adjoint<4>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
+  else if (MM <= 8) hipLaunchKernelGGL(k_adjoint<8>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
+  else hipLaunchKernelGGL(k_adjoint<0>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
 }
+
+int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b) {
+  const unsigned nb = grid1d(n, kRedBlocks);
+  hipLaunchKernelGGL(k_absmax, dim3(nb), dim3(kThreads), 0, s, v, n, b.p_max);
+  return (int)nb;
+}
+
+int forward_blocks(const Geom& g) { return nblocks(forward_grid(g)); }
 
 void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b) {
   hipLaunchKernelGGL(k_merge, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, (const float*)b.adj, out);
@@ -767,32 +1049,36 @@ void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b) {
 
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
   hipLaunchKernelGGL(k_tv, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, (const float*)b.x, (const float*)b.m,
-                     b.wS[0], b.wS[1], b.vs, b.part, b.sc);
+                     b.wS[0], b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc);
 }
 
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot) {
-  hipLaunchKernelGGL(k_hp, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, (const float*)b.adj, out, b.part,
-                     b.sc, gate, with_dot);
+  hipLaunchKernelGGL(k_hp, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, (const float*)b.adj, out, b.p_php,
+                     (const DevScalars*)b.sc, gate, with_dot);
 }
 
-void launch_cginit(const Geom& g, double* stats_row, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_cginit, dim3(red_blocks(g)), dim3(kThreads), 0, s, g, (const float*)b.adj,
-                     (const float*)b.vs, b.r, b.pv, b.part, b.sc, stats_row);
+void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b) {
+  hipLaunchKernelGGL(k_cginit, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.adj,
+                     (const float*)b.vs, b.r, b.pv, b.p_rr[0], (const double*)b.p_wzd, nblocks(forward_grid(g)),
+                     (const double*)b.p_tv, nblocks(tv_grid(g)), b.stats, b.sc);
 }
 
-void launch_cgupd(const Geom& g, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_cgupd, dim3(red_blocks(g)), dim3(kThreads), 0, s, g, b.x, b.r, (const float*)b.pv,
-                     (const float*)b.hp, b.part, b.sc);
+void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b) {
+  hipLaunchKernelGGL(k_cgupd, dim3(g.red_blocks), dim3(kThreads), 0, s, g, b.x, b.r, (const float*)b.pv,
+                     (const float*)b.hp, (const double*)b.p_rr[(step - 1) & 1], b.p_rr[step & 1],
+                     (const double*)b.p_php, nblocks(tv_grid(g)), step, b.sc);
 }
 
-void launch_cgp(const Geom& g, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_cgp, dim3(red_blocks(g)), dim3(kThreads), 0, s, g, (const float*)b.r, b.pv,
+void launch_cgp(const Geom& g, int step, hipStream_t s, const Bufs& b) {
+  hipLaunchKernelGGL(k_cgp, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.r, b.pv,
+                     (const double*)b.p_rr[(step - 1) & 1], (const double*)b.p_rr[step & 1],
                      (const DevScalars*)b.sc);
 }
 
-void launch_iter_end(const Geom& g, double* stats_row, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(64), 0, s, b.sc, stats_row, g.sd > 0 ? 1 : 0);
+void launch_iter_end(const Geom& g, hipStream_t s, const Bufs& b) {
+  hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(kThreads), 0, s, g, (const double*)b.p_rr[0],
+                     (const double*)b.p_rr[1], b.stats, b.sc);
 }
 
 void launch_edge(const Geom& g, const float* x, const float* occ, float* m, hipStream_t s, const Bufs& b, int gate) {
