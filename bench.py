@@ -1,11 +1,16 @@
 """Benchmark of the ADMM light-field super-resolution solve on one MI355X.
 
-One step = one complete solve (lfsr_solve: x0, w = 0, N ADMM iterations of
-K CG steps each, output copy) of the 9x9-view, 1152x1152, x3 workload, with
-the inputs resident in HBM.  Prints one JSON line.
+One step = one complete solve (lfsr_solve: x0, w = 0, N ADMM iterations of K
+CG steps each, output copy) of the 9x9-view, 1152x1152, x3 workload with the
+inputs resident in HBM.  Prints one JSON line: throughput in HR
+Mpixel-views x ADMM iterations per second, the roofline of the dominant kernel
+(its average launch duration measured with HIP events on its launch stream
+over the timed region) and the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -13,9 +18,62 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "HR Mpixel-views x ADMM iters/s + achieved HBM GB/s; p50/p99 job latency"
+UNIT = "HR Mpixel-views x ADMM iters/s"
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0      # MI355X published HBM3E bandwidth
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_flops_per_launch(kind, cfg):
+    """Algorithmic FLOPs of one launch of a kernel kind:
+    forward: per view-pixel 9 (bilinear as three lerps) + 2 kb/zeta
+             (horizontal blur at lattice columns) + 2 kb/zeta^2 (vertical),
+    adjoint: per view-pixel 2 kb/zeta + 2 kb/zeta^2 (polyphase B^T D^T)
+             + 10 (bilinear-transpose weights and accumulation),
+    normal:  per pixel 4 flops per NLTV offset."""
+    H, W = cfg["zeta"] * cfg["sy"], cfg["zeta"] * cfg["sx"]
+    sk, kb, z = cfg["U"] * cfg["V"], cfg["kb"], cfg["zeta"]
+    vp = H * W * sk
+    if kind == "forward":
+        return vp * (9 + 2 * kb / z + 2 * kb / z ** 2)
+    if kind == "adjoint":
+        return vp * (2 * kb / z + 2 * kb / z ** 2 + 10)
+    if kind == "normal":
+        return H * W * 4 * (cfg["win"] ** 2 - 1)
+    return None
+
+
+def bytes_per_iteration(cfg, es=4):
+    """Algorithmic HBM bytes of one ADMM iteration: the state and operator
+    streams each iteration must move at least once (x, disparity, weight map,
+    LR views, both duals read+written, e written and read, v; per CG step
+    p, t = A p written and read, and ten HR-vector passes)."""
+    H, W = cfg["zeta"] * cfg["sy"], cfg["zeta"] * cfg["sx"]
+    p, q = H * W, cfg["sy"] * cfg["sx"]
+    sk, sd, K = cfg["U"] * cfg["V"], cfg["win"] ** 2 - 1, cfg["cg_iter"]
+    wz = p * es + 2 * p * 4 + sk * q * 4 + 2 * (sk * q + sd * p) * es + 2 * sk * q * es + p * 4
+    cg = K * (2 * p * 4 + 2 * sk * q * es + 10 * p * 4)
+    return wz + cg
+
+
+def traffic_from_profiles(kind):
+    """HBM bytes per launch of `kind` from the committed rocprofv3 counter
+    summary, or None if it is absent or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2206_05047_amd", "csrc", "lfsr_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    k = rec.get("kernels", {}).get(kind)
+    if not k or rec.get("kernel_source_sha256") != sha:
+        return None
+    return k.get("hbm_bytes_per_launch")
 
 
 def main():
@@ -24,7 +82,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3")
-    ap.add_argument("--cpu-iters", type=int, default=2, help="ADMM iterations of the oracle CPU baseline sample")
+    ap.add_argument("--cpu-iters", type=int, default=8, help="ADMM iterations of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=0, help="override the ADMM iteration count (profiling only)")
     args = ap.parse_args()
@@ -52,29 +110,61 @@ def main():
     clean = solver.lfsr_forward(torch.from_numpy(sc["x_gt"].astype(np.float32)).cuda(), disp)
     y = torch.from_numpy(synth.degrade(clean.cpu().numpy(), noise)).cuda()
     out = torch.empty((solver.H, solver.W), dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
+    N, K = cfg["n_iter"], cfg["cg_iter"]
+    launches_per_solve = N * (K + 1)
 
-    for _ in range(args.warmup):
+    # warm-up; the first warm-up solve is timed per kernel kind to find the dominant kernel
+    breakdown = None
+    for i in range(max(args.warmup, 1)):
+        if i == 0:
+            solver.lfsr_profile_begin(capacity=launches_per_solve * 6 + 64)
         solver.lfsr_solve(y, disp, out=out, stats=False)
+        if i == 0:
+            breakdown = solver.lfsr_profile_end()
+    torch.cuda.synchronize()
+    dom = max((k for k in breakdown if k in ("forward", "adjoint", "normal", "nltv")),
+              key=lambda k: breakdown[k][0])
+    dom_kind = lfsr.KERNEL_KINDS.index(dom)
+
+    # timed region: K solves; the dominant kernel kind is bracketed by events
+    solver.lfsr_profile_begin(kinds=[dom_kind], capacity=launches_per_solve * 2 * args.steps + 64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         solver.lfsr_solve(y, disp, out=out, stats=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof = solver.lfsr_profile_end()
     stats = solver.lfsr_get_stats()
     ms = (t1 - t0) * 1e3 / max(args.steps, 1)
-    H, W, sk, N = solver.H, solver.W, solver.sk, cfg["n_iter"]
-    pv_iters = H * W * sk * N
-    value = pv_iters * args.steps / (t1 - t0) / 1e6
+    H, W, sk = solver.H, solver.W, solver.sk
+    value = H * W * sk * N * args.steps / (t1 - t0) / 1e6
     x = out.cpu().numpy()
     log(f"[bench] {args.config}: {ms:.2f} ms/solve, PSNR {synth.psnr(x, sc['x_gt']):.2f} dB, "
         f"J_N={stats['objective']:.6g}, iters={stats['iters_run']}")
+    log("[bench] warm-up kernel time per solve (ms): " +
+        ", ".join(f"{k}={v[0]:.1f} ({v[1]})" for k, v in breakdown.items()))
 
+    tot_ms, n_launch = prof[dom]
+    avg_s = tot_ms / max(n_launch, 1) / 1e3
+    flops = kernel_flops_per_launch(dom, cfg)
+    traffic = traffic_from_profiles(dom)
+    if dom == "nltv":
+        bpl = 2 * (cfg["win"] ** 2 - 1) * H * W * 4 + 3 * H * W * 4
+        roof = {"bound": "hbm", "achieved": bpl / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof["kernel"] = dom
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches_timed"] = n_launch
+
+    hbm_gbs = bytes_per_iteration(cfg) * N * args.steps / (t1 - t0) / 1e9
     line = {
-        "metric": "HR Mpixel-views x ADMM iters/s",
+        "metric": METRIC,
         "value": value,
-        "unit": "Mpixel-view-iter/s",
+        "unit": UNIT,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -85,25 +175,29 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": synth.WORKLOAD_TEXT[args.config], "name": args.config, "views": sk,
-                   "hr": [H, W], "scale": cfg["zeta"], "admm_iters": N, "cg_iters": cfg["cg_iter"]},
+                   "hr": [H, W], "scale": cfg["zeta"], "admm_iters": N, "cg_iters": K},
+        "hbm_gbs_algorithmic": hbm_gbs,
+        "hbm_frac_algorithmic": hbm_gbs / PEAK_HBM_GBS,
+        "roofline": roof,
+        "kernel_ms_per_solve": {k: v[0] for k, v in breakdown.items()},
     }
 
     if not args.no_cpu_baseline:
         import oracle
 
         o = oracle.Oracle(cfg)
-        st = o.init_state(y.cpu().numpy())
         yy = y.cpu().numpy()
-        dd = sc["disp"]
+        st = o.init_state(yy)
         tc0 = time.perf_counter()
-        o.iterate(st, yy, dd, count=args.cpu_iters)
+        o.iterate(st, yy, sc["disp"], count=args.cpu_iters)
         tc1 = time.perf_counter()
         line["cpu_baseline"] = {
             "value": H * W * sk * args.cpu_iters / (tc1 - tc0) / 1e6,
-            "unit": "Mpixel-view-iter/s",
+            "unit": UNIT,
             "cores": oracle.Oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{args.cpu_iters} ADMM iterations (K={cfg['cg_iter']}) of the same workload from x0, FP64",
+            "sample": f"{args.cpu_iters} ADMM iterations (K={K}) of the same workload from x0, FP64, "
+                      f"{tc1 - tc0:.1f} s",
         }
     print(json.dumps(line), flush=True)
 

@@ -177,6 +177,26 @@ lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_oc
  * (the x0 of lfsr_init). */
 lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out, void* hip_stream);
 
+/* Kernel timing (tracing aid).  While a profile is open, every launch of a
+ * selected kernel kind issued by this handle is bracketed by two HIP events
+ * recorded on the stream it is launched on; lfsr_profile_end synchronises on
+ * them and returns, per kind, the summed event-measured duration and the
+ * number of timed launches.  capacity bounds the number of timed launches
+ * (the rest run untimed); the events are created by lfsr_profile_begin and
+ * destroyed by lfsr_profile_end.  Opening a second profile is LFSR_ESTATE. */
+typedef enum {
+  LFSR_K_FORWARD = 0, /* A_k x for all views (wz-step and CG variants) */
+  LFSR_K_ADJOINT = 1, /* sum_k A_k^T e_k */
+  LFSR_K_NLTV = 2,    /* NLTV z/w-step and divergence */
+  LFSR_K_NORMAL = 3,  /* normal-operator assembly G^T G p and <p, Hp> */
+  LFSR_K_CG = 4,      /* CG start / update kernels */
+  LFSR_K_OTHER = 5,   /* edge weight, iteration bookkeeping */
+  LFSR_K_COUNT = 6
+} lfsr_kernel_kind;
+
+lfsr_status lfsr_profile_begin(lfsr_handle* h, uint32_t kind_mask, int32_t capacity);
+lfsr_status lfsr_profile_end(lfsr_handle* h, double* h_total_ms, int32_t* h_launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/lfsr.h"
 #include "lfsr_internal.h"
@@ -56,9 +57,9 @@ bool choose_tiles(Geom& g, std::string* err) {
   g.f_vpb = (int)vpb;
 
   // adjoint: prefer >= 1024 tiles; the HR tile must be at least the halo
-  const int acand[6][2] = {{16, 8}, {8, 8}, {8, 4}, {4, 4}, {4, 2}, {2, 2}};
+  const int acand[7][2] = {{16, 8}, {8, 8}, {8, 4}, {4, 8}, {4, 4}, {4, 2}, {4, 1}};
   int best = -1;
-  for (int ci = 0; ci < 6; ++ci) {
+  for (int ci = 0; ci < 7; ++ci) {
     Geom t = g;
     t.a_tly = acand[ci][0];
     t.a_tlx = acand[ci][1];
@@ -221,7 +222,16 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
 
 }  // namespace
 
+struct Profile {
+  bool on = false;
+  uint32_t mask = 0;
+  std::vector<hipEvent_t> ev;  // pairs
+  std::vector<int> kind;
+  int used = 0;
+};
+
 struct lfsr_handle {
+  Profile prof;
   lfsr_params prm;
   Plan plan;
   Bufs b;
@@ -261,26 +271,41 @@ lfsr_status usable(lfsr_handle* h) {
 
 hipStream_t S(void* s) { return (hipStream_t)s; }
 
+// Bracket a launch with profiling events when its kind is being timed.
+template <class F>
+void timed(lfsr_handle* h, int kind, hipStream_t s, F&& launch) {
+  Profile& pr = h->prof;
+  const bool t = pr.on && (pr.mask >> kind & 1u) && (size_t)(2 * pr.used + 1) < pr.ev.size();
+  if (t) (void)hipEventRecord(pr.ev[2 * pr.used], s);
+  launch();
+  if (t) {
+    (void)hipEventRecord(pr.ev[2 * pr.used + 1], s);
+    pr.kind[pr.used] = kind;
+    ++pr.used;
+  }
+}
+
 // One ADMM iteration (Algorithm 1 with the CG x-step of Algorithm 2).
 void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   const Geom& g = h->plan.g;
   const Bufs& b = h->b;
   // weights from x^(n-1) (sec 7.1: recomputed every iteration when reweighting)
-  launch_edge(g, b.x, h->occ, b.m, s, b, kGateAdmm | kGateReweight);
+  timed(h, LFSR_K_OTHER, s, [&] { launch_edge(g, b.x, h->occ, b.m, s, b, kGateAdmm | kGateReweight); });
   // z/w-steps of both blocks; e and the NLTV divergence feed v
-  launch_forward_wzd(g, b.x, h->disp, h->y, s, b);
-  if (g.sd > 0) launch_tv(g, s, b);
-  launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm, forward_blocks(g));
-  launch_cginit(g, s, b);
+  timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_wzd(g, b.x, h->disp, h->y, s, b); });
+  if (g.sd > 0) timed(h, LFSR_K_NLTV, s, [&] { launch_tv(g, s, b); });
+  timed(h, LFSR_K_ADJOINT, s, [&] { launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm, forward_blocks(g)); });
+  timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b); });
   // x-step: K CG steps on G^T G delta = -v, accumulated straight into x
   for (int k = 1; k <= h->prm.cg_iters; ++k) {
-    launch_forward(g, b.pv, h->disp, b.lr, s, b, kGateAdmm | kGateCg);
-    launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g));
-    launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1);
-    launch_cgupd(g, k, s, b);
-    launch_cgp(g, k, s, b);
+    timed(h, LFSR_K_FORWARD, s, [&] { launch_forward(g, b.pv, h->disp, b.lr, s, b, kGateAdmm | kGateCg); });
+    timed(h, LFSR_K_ADJOINT, s,
+          [&] { launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g)); });
+    timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1); });
+    timed(h, LFSR_K_CG, s, [&] { launch_cgupd(g, k, s, b); });
+    timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });
   }
-  launch_iter_end(g, s, b);
+  timed(h, LFSR_K_OTHER, s, [&] { launch_iter_end(g, s, b); });
   h->n_done += 1;
 }
 
@@ -342,7 +367,11 @@ lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, l
   return LFSR_OK;
 }
 
-void lfsr_destroy(lfsr_handle* h) { delete h; }
+void lfsr_destroy(lfsr_handle* h) {
+  if (!h) return;
+  for (hipEvent_t e : h->prof.ev) (void)hipEventDestroy(e);
+  delete h;
+}
 
 const char* lfsr_last_error(const lfsr_handle* h) { return h ? h->err.c_str() : g_thread_err.c_str(); }
 
@@ -512,6 +541,58 @@ lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out
   if (!d_lr_view || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
   launch_bicubic(h->plan.g, d_lr_view, d_hr_out, S(hip_stream));
   return check_hip(h, "lfsr_bicubic");
+}
+
+lfsr_status lfsr_profile_begin(lfsr_handle* h, uint32_t kind_mask, int32_t capacity) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (h->prof.on) return set_err(h, LFSR_ESTATE, "a profile is already open");
+  if (capacity < 1 || capacity > (1 << 20)) return set_err(h, LFSR_EINVAL, "capacity must be in 1..2^20");
+  Profile& pr = h->prof;
+  pr.ev.assign(2 * (size_t)capacity, nullptr);
+  pr.kind.assign((size_t)capacity, 0);
+  for (auto& e : pr.ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : pr.ev)
+        if (f) (void)hipEventDestroy(f);
+      pr.ev.clear();
+      return check_hip(h, "lfsr_profile_begin event create");
+    }
+  }
+  pr.mask = kind_mask;
+  pr.used = 0;
+  pr.on = true;
+  return LFSR_OK;
+}
+
+lfsr_status lfsr_profile_end(lfsr_handle* h, double* h_total_ms, int32_t* h_launches) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  Profile& pr = h->prof;
+  if (!pr.on) return set_err(h, LFSR_ESTATE, "no profile is open");
+  double tot[LFSR_K_COUNT] = {0};
+  int cnt[LFSR_K_COUNT] = {0};
+  lfsr_status res = LFSR_OK;
+  if (pr.used > 0 && hipEventSynchronize(pr.ev[2 * pr.used - 1]) != hipSuccess) res = check_hip(h, "profile sync");
+  for (int i = 0; i < pr.used && res == LFSR_OK; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.ev[2 * i], pr.ev[2 * i + 1]) != hipSuccess) {
+      res = check_hip(h, "profile elapsed");
+      break;
+    }
+    tot[pr.kind[i]] += ms;
+    cnt[pr.kind[i]] += 1;
+  }
+  for (hipEvent_t e : pr.ev) (void)hipEventDestroy(e);
+  pr.ev.clear();
+  pr.kind.clear();
+  pr.on = false;
+  pr.used = 0;
+  for (int k = 0; k < LFSR_K_COUNT; ++k) {
+    if (h_total_ms) h_total_ms[k] = tot[k];
+    if (h_launches) h_launches[k] = cnt[k];
+  }
+  return res;
 }
 
 }  // extern "C"

@@ -14,10 +14,11 @@ constexpr int kThreads = 256;     // every kernel runs 256-thread (4 x wave64) b
 // forward operator: blur positions, horizontal-pass outputs per thread
 constexpr int kFwdSlots = 12;     // NY*NX <= 256*kFwdSlots
 constexpr int kFwdHSlots = 5;     // NY*tlx <= 256*kFwdHSlots
-// adjoint: HR pixels, vertical-pass outputs and LR tile values per thread
-constexpr int kAdjSlots = 6;      // TH*TW <= 256*kAdjSlots
-constexpr int kAdjVSlots = 4;     // TH*LX <= 256*kAdjVSlots
-constexpr int kAdjESlots = 2;     // LY*LX <= 256*kAdjESlots
+// adjoint (per wave: a quarter of the tile's HR rows): HR pixels,
+// vertical-pass outputs and staged LR values per lane
+constexpr int kAdjSlots = 5;      // (TH/4)*TW <= 64*kAdjSlots
+constexpr int kAdjVSlots = 4;     // (TH/4)*LX <= 64*kAdjVSlots
+constexpr int kAdjESlots = 3;     // RL*LX <= 64*kAdjESlots
 
 constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles (4 rows per thread)
 constexpr int kRedBlocks = 1024;  // max grid of the element-wise CG kernels (= partials per reduction)

@@ -83,6 +83,35 @@ __device__ __forceinline__ double* stats_row(const Geom& g, double* stats, const
   return stats + (size_t)r * 6;
 }
 
+// Stage a rows x cols tile, element (r, c) = src[(Y0 + r) * W + X0 + c] (zero
+// outside [0,H) x [0,W)), into dst[r * ld + c].  Every thread issues a batch
+// of loads (clamped, always in-bounds addresses) before any LDS store, so the
+// global-memory latency is paid once per batch rather than once per element.
+template <int BATCH = 8>
+__device__ __forceinline__ void stage_tile(float* __restrict__ dst, int ld, const float* __restrict__ src, int H, int W,
+                                           int Y0, int X0, int rows, int cols) {
+  const int n = rows * cols;
+  const float inv = 1.f / (float)cols;  // (e + 1/2)/cols in float floors exactly for e < 2^16, cols < 400
+  for (int base = threadIdx.x; base < n; base += kThreads * BATCH) {
+    float v[BATCH];
+    int off[BATCH];
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j) {
+      const int e = base + j * kThreads;
+      const int r = (int)(((float)e + 0.5f) * inv), c = e - r * cols;
+      const int Y = Y0 + r, X = X0 + c;
+      const bool ok = e < n && Y >= 0 && Y < H && X >= 0 && X < W;
+      const int Yc = min(max(Y, 0), H - 1), Xc = min(max(X, 0), W - 1);
+      const float t = src[(size_t)Yc * W + Xc];
+      v[j] = ok ? t : 0.f;
+      off[j] = e < n ? r * ld + c : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j)
+      if (off[j] >= 0) dst[off[j]] = v[j];
+  }
+}
+
 // Sum of the per-tile adjoint partial images that cover HR pixel (Y, X).
 __device__ __forceinline__ float adj_merge(const Geom& g, const float* __restrict__ adj, int Y, int X) {
   // (Y + 1/2) / a_th in float: the quotient is at least 1/(2 a_th) away from
@@ -114,7 +143,7 @@ __device__ __forceinline__ float adj_merge(const Geom& g, const float* __restric
 // A^T, e = lambda2 r + (vartheta/2) lambda1 (2 w_D' - w_D), written to `out`;
 // per-block partials {sum|r|, sum r^2, sum (w_D'-w_D)^2} go to `part`.
 // grid = (ceil(sx/f_tlx), ceil(sy/f_tly), ceil(sk/f_vpb)).
-template <bool WZD>
+template <bool WZD, int KBT>  // KBT: compile-time blur size (0: runtime g.kb)
 __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __restrict__ src,
                                                       const float* __restrict__ disp, float* __restrict__ out,
                                                       const float* __restrict__ y, float* __restrict__ wD,
@@ -122,7 +151,8 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
                                                       const DevScalars* __restrict__ sc, int gate) {
   if (gated(sc, g, gate)) return;
   extern __shared__ float smem[];
-  const int zeta = g.zeta, rb = g.rb, h = g.halo, kb = g.kb;
+  const int zeta = g.zeta, rb = g.rb, h = g.halo;
+  const int kb = KBT > 0 ? KBT : g.kb;
   const int tly = g.f_tly, tlx = g.f_tlx;
   const int NY = (tly - 1) * zeta + 1 + 2 * rb;
   const int NX = (tlx - 1) * zeta + 1 + 2 * rb;
@@ -135,11 +165,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
   const int Yp0 = i0 * zeta - rb, Xp0 = j0 * zeta - rb;
   const int tid = threadIdx.x;
 
-  for (int idx = tid; idx < SY * SX; idx += kThreads) {
-    const int ty = idx / SX, tx = idx - ty * SX;
-    const int Y = Yp0 - h + ty, X = Xp0 - h + tx;
-    xs[idx] = (Y >= 0 && Y < g.H && X >= 0 && X < g.W) ? src[(size_t)Y * g.W + X] : 0.f;
-  }
+  stage_tile(xs, SX, src, g.H, g.W, Yp0 - h, Xp0 - h, SY, SX);
+  // (idx + 1/2) / n in float: exact floor division for idx < 2^22
+  const float invNX = 1.f / (float)NX, invTLX = 1.f / (float)tlx;
   // Blur positions of this thread: disparity clamped to +-disp_bound (which
   // keeps every gather inside the tile) and 0 outside the image, where the
   // zero tile makes the sample vanish as the zero padding of B requires.
@@ -147,29 +175,30 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
   int base[kFwdSlots];
   int rbase[kFwdSlots];   // base + row offset of the current angular row
   float fyv[kFwdSlots];   // vertical bilinear weight of the current angular row
+  {
+    int pofs[kFwdSlots];
 #pragma unroll
-  for (int s = 0; s < kFwdSlots; ++s) {
-    const int idx = tid + s * kThreads;
-    float w = 0.f;
-    int b = 0;
-    if (idx < NPOS) {
-      const int py = idx / NX, px = idx - py * NX;
+    for (int s = 0; s < kFwdSlots; ++s) {  // all loads first (in-bounds addresses), then the math
+      const int idx = tid + s * kThreads;
+      const int py = (int)(((float)idx + 0.5f) * invNX), px = idx - py * NX;
       const int Y = Yp0 + py, X = Xp0 + px;
-      if (Y >= 0 && Y < g.H && X >= 0 && X < g.W)
-        w = fminf(fmaxf(disp[(size_t)Y * g.W + X], -g.disp_bound), g.disp_bound);
-      b = (py + h) * SX + (px + h);
+      const bool in = idx < NPOS && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
+      pofs[s] = in ? Y * g.W + X : -1;
+      om[s] = disp[in ? (size_t)Y * g.W + X : 0];
+      base[s] = idx < NPOS ? (py + h) * SX + (px + h) : 0;
     }
-    om[s] = w;
-    base[s] = b;
+#pragma unroll
+    for (int s = 0; s < kFwdSlots; ++s)
+      om[s] = pofs[s] >= 0 ? fminf(fmaxf(om[s], -g.disp_bound), g.disp_bound) : 0.f;
   }
   int hoff[kFwdHSlots];
 #pragma unroll
   for (int s = 0; s < kFwdHSlots; ++s) {
     const int idx = tid + s * kThreads;
-    const int py = idx / tlx, j = idx - py * tlx;
+    const int py = (int)(((float)idx + 0.5f) * invTLX), j = idx - py * tlx;
     hoff[s] = idx < NH ? py * NX + j * zeta : 0;
   }
-  const int li = tid / tlx, lj = tid - li * tlx;
+  const int li = (int)(((float)tid + 0.5f) * invTLX), lj = tid - li * tlx;
   const int oi = i0 + li, oj = j0 + lj;
   const bool vout = tid < tly * tlx && oi < g.sy && oj < g.sx;
   const int voff = li * zeta * tlx + lj;
@@ -221,8 +250,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
     float hsum[kFwdHSlots];
 #pragma unroll
     for (int s = 0; s < kFwdHSlots; ++s) hsum[s] = 0.f;
-#pragma unroll 4
-    for (int b = 0; b < kb; ++b) {
+#pragma unroll
+    for (int b = 0; b < (KBT > 0 ? KBT : kMaxTaps); ++b) {
+      if (KBT == 0 && b >= kb) break;
       const float gb = g.g[b];
 #pragma unroll
       for (int s = 0; s < kFwdHSlots; ++s) hsum[s] = fmaf(gb, wv[hoff[s] + b], hsum[s]);
@@ -236,8 +266,11 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
     // B, vertical pass, only at the lattice rows; then the fused epilogue
     if (vout) {
       float t = 0.f;
-#pragma unroll 4
-      for (int a = 0; a < kb; ++a) t = fmaf(g.g[a], hb[voff + a * tlx], t);
+#pragma unroll
+      for (int a = 0; a < (KBT > 0 ? KBT : kMaxTaps); ++a) {
+        if (KBT == 0 && a >= kb) break;
+        t = fmaf(g.g[a], hb[voff + a * tlx], t);
+      }
       if constexpr (!WZD) {
         out[o] = t;
         vmax = fmaxf(vmax, fabsf(t));
@@ -279,16 +312,23 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
 // Adjoint sum_k A_k^T lr_k = sum_k W_k^T B^T D^T lr_k into per-tile partial
 // images [tile][a_ey][a_ex] (HR tile + warp halo).  grid = (a_ntx, a_nty).
 //
-// The scatter W_k^T accumulates in 64-bit fixed point in LDS (ds_add_u64):
-// LDS float atomics run ~30x slower than integer ones on this part, and
-// integer addition is associative, so the sums are also bitwise reproducible.
-// Every contribution c = u * w has |c| <= M = max |lr| (the polyphase taps and
-// the bilinear weights are non-negative and sum to at most 1), so with
-// S = 2^(30 - ceil(log2 M)) each c * S rounds to an int32 without saturation
-// (resolution 2^-30 M per contribution) and at most sk*(2 halo + 1)^2
-// contributions per cell keep the 64-bit sum far from overflow.  M comes from
+// Each of the four waves owns a quarter of the tile's HR rows and walks all
+// views on its own: it stages the LR rows its rows need in a wave-private LDS
+// buffer (prefetched one view ahead), applies B^T D^T as a polyphase
+// separable filter, and scatters W_k^T with the bilinear weights of W_k into
+// the block's shared accumulator.  No block barrier is needed inside the view
+// loop (LDS operations of one wave complete in order).
+//
+// The accumulator is 64-bit fixed point (ds_add_u64): LDS float atomics run
+// ~30x slower than integer ones on this part, and integer addition is
+// associative, so the sums are also bitwise reproducible.  Every contribution
+// c = u * w has |c| <= M = max |lr| (the polyphase taps and the bilinear
+// weights are non-negative and sum to at most 1), so with
+// S = 2^(30 - ceil(log2 M)) each c * S truncates to an int32 without
+// saturation (resolution 2^-29 M per contribution) and at most
+// sk*(2 halo + 1)^2 contributions per cell stay far below 2^63.  M comes from
 // the producer's per-block maxima (`pmax`, npmax of them).
-template <int MMT>  // compile-time bound on the taps per polyphase phase (0: taps read from LDS)
+template <int MMT>  // compile-time taps per polyphase phase, exactly (2 rb)/zeta + 1 (0: runtime, taps in LDS)
 __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __restrict__ lr,
                                                       const float* __restrict__ disp, float* __restrict__ outp,
                                                       const float* __restrict__ pmax, int npmax,
@@ -298,20 +338,21 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
   float* smem = reinterpret_cast<float*>(smem8);
   const int zeta = g.zeta, rb = g.rb, h = g.halo, kb = g.kb;
   const int TH = g.a_th, TW = g.a_tw, EY = g.a_ey, EX = g.a_ex;
+  const int RH = TH / 4;                           // HR rows per wave
   const int ci = (rb + zeta - 1) / zeta;           // LR rows/cols within blur reach
-  const int LY = g.a_tly + 2 * ci, LX = g.a_tlx + 2 * ci;
-  const int MM = (2 * rb) / zeta + 1;              // max lattice points within +-rb
+  const int LX = g.a_tlx + 2 * ci;
+  const int RL = RH / zeta + 2 * ci;               // LR rows a wave stages
+  const int MM = MMT > 0 ? MMT : (2 * rb) / zeta + 1;  // lattice points within +-rb
   const int PAD = zeta * MM;                       // zero taps below index 0 (indices reach 1 - zeta*MM)
-  const int ETS = (LY + MM) * LX, HVS = TH * LX + MM;
-  long long* acc = smem8;            // [EY][EX] fixed-point accumulator
-  float* et = smem + 2 * EY * EX;    // [2][LY+MM][LX] LR tile (double buffered, zero-padded rows)
-  float* hv = et + 2 * ETS;          // [2][TH*LX + MM] vertical B^T pass
-  float* gs = hv + 2 * HVS;          // [PAD + kb] taps, zeros below
-  const int tid = threadIdx.x;
+  const int ETS = (RL + MM) * LX, HVS = RH * LX + MM;
+  long long* acc = smem8;                          // [EY][EX] fixed-point accumulator
+  float* gs = smem + 2 * EY * EX;                  // [PAD + kb] taps, zeros below
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* e_ = gs + PAD + kb + wave * (ETS + HVS);  // wave-private LR rows (zero-padded)
+  float* h_ = e_ + ETS;                            // wave-private vertical pass
   for (int idx = tid; idx < EY * EX; idx += kThreads) acc[idx] = 0;
-  for (int idx = tid; idx < 2 * ETS; idx += kThreads) et[idx] = 0.f;
-  for (int idx = tid; idx < 2 * HVS; idx += kThreads) hv[idx] = 0.f;
   for (int idx = tid; idx < PAD + kb; idx += kThreads) gs[idx] = idx < PAD ? 0.f : g.g[idx - PAD];
+  for (int idx = lane; idx < ETS + HVS; idx += 64) e_[idx] = 0.f;
 
   // fixed-point scale from the producer's block maxima (order-free, so exact)
   float mloc = 0.f;
@@ -319,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
   __shared__ float smax[4];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, off, 64));
-  if ((tid & 63) == 0) smax[tid >> 6] = mloc;
+  if (lane == 0) smax[wave] = mloc;
   __syncthreads();
   const float M = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
   int eM = 0;
@@ -330,50 +371,59 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
   const int ty = blockIdx.y, tx = blockIdx.x;
   const int i0 = ty * g.a_tly, j0 = tx * g.a_tlx;
   const int Y0 = i0 * zeta, X0 = j0 * zeta;
-  const int nslot = (TH * TW + kThreads - 1) / kThreads;  // uniform
+  const int ly0 = wave * RH;                       // first HR row of this wave (tile-local)
+  const int li0 = i0 + ly0 / zeta - ci;            // first LR row the wave stages
+  const float invLX = 1.f / (float)LX, invTW = 1.f / (float)TW;  // (e + 1/2)/n floors exactly here
 
-  // LR tile values this thread stages (global offset within a view, -1 = zero)
+  // LR values this lane stages per view (offset within a view; -1 = zero)
   int eoff[kAdjESlots];
 #pragma unroll
   for (int s = 0; s < kAdjESlots; ++s) {
-    const int idx = tid + s * kThreads;
-    const int a = idx / LX, b = idx - a * LX;
-    const int i = i0 - ci + a, j = j0 - ci + b;
-    eoff[s] = (idx < LY * LX && i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? i * g.sx + j : -1;
+    const int idx = lane + s * 64;
+    const int a = (int)(((float)idx + 0.5f) * invLX), b = idx - a * LX;
+    const int i = li0 + a, j = j0 - ci + b;
+    eoff[s] = (idx < RL * LX && i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? i * g.sx + j : -1;
   }
-  // vertical-pass outputs (ly, b): LR rows i = Y div zeta + m, m in [m_lo, m_lo + MM),
-  // tap Y - zeta i + rb (zero beyond the kernel)
+  // vertical outputs (wave row r, LR col b): LR rows i = Y div zeta + m for m in [m_lo, m_lo + MM)
   int vbase[kAdjVSlots], vtap[kAdjVSlots];
 #pragma unroll
   for (int s = 0; s < kAdjVSlots; ++s) {
-    const int idx = tid + s * kThreads;
-    const int ly = idx / LX, b = idx - ly * LX;
-    const int ph = ly % zeta, lq = ly / zeta;
+    const int idx = lane + s * 64;
+    const int r = (int)(((float)idx + 0.5f) * invLX), b = idx - r * LX;
+    const int ly = ly0 + r;
+    const int ph = ly % zeta;
     const int mlo = floordiv(ph - rb + zeta - 1, zeta);
-    vbase[s] = idx < TH * LX ? (lq + mlo + ci) * LX + b : 0;
+    // staged row of LR row (Y0 + ly) div zeta + mlo
+    vbase[s] = idx < RH * LX ? ((Y0 + ly) / zeta + mlo - li0) * LX + b : 0;
     vtap[s] = PAD + ph - zeta * mlo + rb;
   }
-  // scatter pixels: disparity (clamped), horizontal-pass base/tap, accumulator base
+  // scatter pixels (wave row r, col lx): disparity (clamped), horizontal base/tap, accumulator base
   float om[kAdjSlots];
   int hbase[kAdjSlots], htap[kAdjSlots], abase[kAdjSlots];
   bool act[kAdjSlots];
 #pragma unroll
   for (int s = 0; s < kAdjSlots; ++s) {
-    const int idx = tid + s * kThreads;
-    const int ly = idx / TW, lx = idx - ly * TW;
+    const int idx = lane + s * 64;
+    const int r = (int)(((float)idx + 0.5f) * invTW), lx = idx - r * TW;
+    const int ly = ly0 + r;
     const int Y = Y0 + ly, X = X0 + lx;
-    act[s] = idx < TH * TW && Y < g.H && X < g.W;
-    om[s] = act[s] ? fminf(fmaxf(disp[(size_t)Y * g.W + X], -g.disp_bound), g.disp_bound) : 0.f;
+    act[s] = idx < RH * TW && Y < g.H && X < g.W;
+    om[s] = disp[act[s] ? (size_t)Y * g.W + X : 0];  // batched, in bounds
     const int ph = lx % zeta, lq = lx / zeta;
     const int mlo = floordiv(ph - rb + zeta - 1, zeta);
-    hbase[s] = act[s] ? ly * LX + lq + mlo + ci : 0;
+    hbase[s] = act[s] ? r * LX + lq + mlo + ci : 0;
     htap[s] = PAD + ph - zeta * mlo + rb;
     abase[s] = (ly + h) * EX + (lx + h);
   }
+#pragma unroll
+  for (int s = 0; s < kAdjSlots; ++s) om[s] = act[s] ? fminf(fmaxf(om[s], -g.disp_bound), g.disp_bound) : 0.f;
   float ereg[kAdjESlots];
 #pragma unroll
-  for (int s = 0; s < kAdjESlots; ++s) ereg[s] = eoff[s] >= 0 ? lr[eoff[s]] : 0.f;
-  __syncthreads();  // gs ready
+  for (int s = 0; s < kAdjESlots; ++s) {
+    const float t = lr[eoff[s] >= 0 ? eoff[s] : 0];
+    ereg[s] = eoff[s] >= 0 ? t : 0.f;
+  }
+  __syncthreads();  // accumulator zeroed, taps ready
   // polyphase taps in registers; the horizontal ones carry the fixed-point scale S
   constexpr int RT = MMT > 0 ? MMT : 1;
   float vt[kAdjVSlots][RT], ht[kAdjSlots][RT];
@@ -381,11 +431,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
 #pragma unroll
     for (int s = 0; s < kAdjVSlots; ++s)
 #pragma unroll
-      for (int m = 0; m < MMT; ++m) vt[s][m] = m < MM ? gs[vtap[s] - zeta * m] : 0.f;
+      for (int m = 0; m < MMT; ++m) vt[s][m] = gs[vtap[s] - zeta * m];
 #pragma unroll
     for (int s = 0; s < kAdjSlots; ++s)
 #pragma unroll
-      for (int m = 0; m < MMT; ++m) ht[s][m] = m < MM ? gs[htap[s] - zeta * m] * S : 0.f;
+      for (int m = 0; m < MMT; ++m) ht[s][m] = gs[htap[s] - zeta * m] * S;
   }
 
   unsigned long long* accu = reinterpret_cast<unsigned long long*>(acc);
@@ -395,18 +445,18 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
   int rowoff[kAdjSlots];
   float wy0[kAdjSlots], wy1[kAdjSlots];
   for (int k = 0; k < g.sk; ++k) {
-    const int buf = k & 1;
-    float* e_ = et + buf * ETS;
-    float* h_ = hv + buf * HVS;
 #pragma unroll
     for (int s = 0; s < kAdjESlots; ++s) {
-      const int idx = tid + s * kThreads;
-      if (idx < LY * LX) e_[idx] = ereg[s];
+      const int idx = lane + s * 64;
+      if (idx < RL * LX) e_[idx] = ereg[s];
     }
-    if (k + 1 < g.sk) {  // prefetch the next view's LR tile
+    if (k + 1 < g.sk) {  // prefetch the next view's LR rows
       const float* ln = lr + (size_t)(k + 1) * g.q;
 #pragma unroll
-      for (int s = 0; s < kAdjESlots; ++s) ereg[s] = eoff[s] >= 0 ? ln[eoff[s]] : 0.f;
+      for (int s = 0; s < kAdjESlots; ++s) {
+        const float t = ln[eoff[s] >= 0 ? eoff[s] : 0];
+        ereg[s] = eoff[s] >= 0 ? t : 0.f;
+      }
     }
     // the vertical warp coordinate is shared by the views of an angular row
     const int ka = k / g.V, kbcol = k - ka * g.V;
@@ -421,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
         rowoff[s] = (int)fy0 * EX;
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     // B^T D^T, vertical
     float vv[kAdjVSlots];
 #pragma unroll
@@ -429,10 +479,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
     if constexpr (MMT > 0) {
 #pragma unroll
       for (int m = 0; m < MMT; ++m) {
-        if (m < MM) {
 #pragma unroll
-          for (int s = 0; s < kAdjVSlots; ++s) vv[s] = fmaf(vt[s][m], e_[vbase[s] + m * LX], vv[s]);
-        }
+        for (int s = 0; s < kAdjVSlots; ++s) vv[s] = fmaf(vt[s][m], e_[vbase[s] + m * LX], vv[s]);
       }
     } else {
       for (int m = 0; m < MM; ++m) {
@@ -442,24 +490,32 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
     }
 #pragma unroll
     for (int s = 0; s < kAdjVSlots; ++s) {
-      const int idx = tid + s * kThreads;
-      if (idx < TH * LX) h_[idx] = vv[s];
+      const int idx = lane + s * 64;
+      if (idx < RH * LX) h_[idx] = vv[s];
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     // B^T D^T, horizontal (scaled by S); then W_k^T: send u back to the four taps W_k read
     const float rho = (float)(kbcol - (g.V - 1) / 2);
+    float uu[kAdjSlots];
+#pragma unroll
+    for (int s = 0; s < kAdjSlots; ++s) uu[s] = 0.f;
+    if constexpr (MMT > 0) {
+#pragma unroll
+      for (int m = 0; m < MMT; ++m) {
+#pragma unroll
+        for (int s = 0; s < kAdjSlots; ++s) uu[s] = fmaf(ht[s][m], h_[hbase[s] + m], uu[s]);
+      }
+    } else {
+      for (int m = 0; m < MM; ++m) {
+#pragma unroll
+        for (int s = 0; s < kAdjSlots; ++s) uu[s] = fmaf(gs[htap[s] - zeta * m] * S, h_[hbase[s] + m], uu[s]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int s = 0; s < kAdjSlots; ++s) {
-      if (s >= nslot) break;
-      float u = 0.f;
-      if constexpr (MMT > 0) {
-#pragma unroll
-        for (int m = 0; m < MMT; ++m)
-          if (m < MM) u = fmaf(ht[s][m], h_[hbase[s] + m], u);
-      } else {
-        for (int m = 0; m < MM; ++m) u = fmaf(gs[htap[s] - zeta * m] * S, h_[hbase[s] + m], u);
-      }
       if (!act[s]) continue;
+      const float u = uu[s];
       const float sx = rho * om[s];
       const float fx0 = floorf(sx);
       const float fx = sx - fx0, gx = 1.f - fx;
@@ -588,13 +644,8 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict
   float* xs = smem;
   float* ms = xs + LYd * LXd;
   const int X0 = blockIdx.x * kTvTileX, Y0 = blockIdx.y * kTvTileY;
-  for (int idx = threadIdx.x; idx < LYd * LXd; idx += kThreads) {
-    const int a = idx / LXd, b = idx - a * LXd;
-    const int Y = Y0 - rw + a, X = X0 - rw + b;
-    const bool in = Y >= 0 && Y < g.H && X >= 0 && X < g.W;
-    xs[idx] = in ? x[(size_t)Y * g.W + X] : 0.f;
-    ms[idx] = in ? m[(size_t)Y * g.W + X] : 0.f;
-  }
+  stage_tile(xs, LXd, x, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
+  stage_tile(ms, LXd, m, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
   __syncthreads();
   const float* wo = sc->wcur ? ws1 : ws0;
   float* wn_ = sc->wcur ? ws0 : ws1;
@@ -646,14 +697,10 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
   const int X0 = blockIdx.x * kTvTileX, Y0 = blockIdx.y * kTvTileY;
   const int tid = threadIdx.x;
   if (g.sd > 0) {
-    for (int idx = tid; idx < LYd * LXd; idx += kThreads) {
-      const int a = idx / LXd, b = idx - a * LXd;
-      const int Y = Y0 - rw + a, X = X0 - rw + b;
-      const bool in = Y >= 0 && Y < g.H && X >= 0 && X < g.W;
-      ps[idx] = in ? pv[(size_t)Y * g.W + X] : 0.f;
-      const float mv = in ? m[(size_t)Y * g.W + X] : 0.f;
-      m2[idx] = mv * mv;
-    }
+    stage_tile(ps, LXd, pv, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
+    stage_tile(m2, LXd, m, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
+    __syncthreads();
+    for (int idx = tid; idx < LYd * LXd; idx += kThreads) m2[idx] = m2[idx] * m2[idx];
   }
   __syncthreads();
   const bool interior = X0 - rw >= 0 && X0 + kTvTileX + rw <= g.W && Y0 - rw >= 0 && Y0 + kTvTileY + rw <= g.H;
@@ -986,15 +1033,18 @@ static inline void adj_dims(const Geom& g, int& ci, int& LY, int& LX, int& MM, i
 size_t adjoint_lds(const Geom& g) {
   int ci, LY, LX, MM, PAD;
   adj_dims(g, ci, LY, LX, MM, PAD);
-  const size_t ets = (size_t)(LY + MM) * LX, hvs = (size_t)g.a_th * LX + MM;
-  return sizeof(float) * (2 * (size_t)g.a_ey * g.a_ex + 2 * ets + 2 * hvs + PAD + g.kb);
+  const int RH = g.a_th / 4, RL = RH / g.zeta + 2 * ci;
+  const size_t ets = (size_t)(RL + MM) * LX, hvs = (size_t)RH * LX + MM;
+  return sizeof(float) * (2 * (size_t)g.a_ey * g.a_ex + PAD + g.kb + 4 * (ets + hvs));
 }
 
 bool adjoint_tile_ok(const Geom& g) {
   int ci, LY, LX, MM, PAD;
   adj_dims(g, ci, LY, LX, MM, PAD);
-  return g.a_th >= g.halo && g.a_tw >= g.halo && g.a_th * g.a_tw <= kThreads * kAdjSlots &&
-         g.a_th * LX <= kThreads * kAdjVSlots && LY * LX <= kThreads * kAdjESlots && adjoint_lds(g) <= 60 * 1024;
+  if (g.a_tly % 4 != 0) return false;  // each wave owns a whole number of LR rows
+  const int RH = g.a_th / 4, RL = RH / g.zeta + 2 * ci;
+  return g.a_th >= g.halo && g.a_tw >= g.halo && RH * g.a_tw <= 64 * kAdjSlots && RH * LX <= 64 * kAdjVSlots &&
+         RL * LX <= 64 * kAdjESlots && adjoint_lds(g) <= 60 * 1024;
 }
 
 size_t tv_lds(const Geom& g) {
@@ -1009,16 +1059,33 @@ dim3 tv_grid(const Geom& g) { return dim3((g.W + kTvTileX - 1) / kTvTileX, (g.H 
 
 static inline int nblocks(dim3 d) { return (int)(d.x * d.y * d.z); }
 
+template <bool WZD>
+static void launch_fwd_kb(const Geom& g, const float* src, const float* disp, float* out, const float* y, float* wD,
+                          double* part, float* pmax, const DevScalars* sc, int gate, hipStream_t s) {
+  const dim3 grid = forward_grid(g), blk(kThreads);
+  const size_t lds = forward_lds(g);
+#define LFSR_FWD(KB) hipLaunchKernelGGL((k_forward<WZD, KB>), grid, blk, lds, s, g, src, disp, out, y, wD, part, pmax, sc, gate)
+  switch (g.kb) {
+    case 1: LFSR_FWD(1); break;
+    case 3: LFSR_FWD(3); break;
+    case 5: LFSR_FWD(5); break;
+    case 7: LFSR_FWD(7); break;
+    case 9: LFSR_FWD(9); break;
+    case 11: LFSR_FWD(11); break;
+    case 13: LFSR_FWD(13); break;
+    default: LFSR_FWD(0); break;
+  }
+#undef LFSR_FWD
+}
+
 void launch_forward(const Geom& g, const float* src, const float* disp, float* out, hipStream_t s,
                     const Bufs& b, int gate) {
-  hipLaunchKernelGGL(k_forward<false>, forward_grid(g), dim3(kThreads), forward_lds(g), s, g, src, disp, out,
-                     (const float*)nullptr, (float*)nullptr, (double*)nullptr, b.p_max, (const DevScalars*)b.sc, gate);
+  launch_fwd_kb<false>(g, src, disp, out, nullptr, nullptr, nullptr, b.p_max, b.sc, gate, s);
 }
 
 void launch_forward_wzd(const Geom& g, const float* src, const float* disp, const float* y, hipStream_t s,
                         const Bufs& b) {
-  hipLaunchKernelGGL(k_forward<true>, forward_grid(g), dim3(kThreads), forward_lds(g), s, g, src, disp, b.lr, y,
-                     b.wD, b.p_wzd, b.p_max, (const DevScalars*)b.sc, (int)kGateAdmm);
+  launch_fwd_kb<true>(g, src, disp, b.lr, y, b.wD, b.p_wzd, b.p_max, b.sc, (int)kGateAdmm, s);
 }
 
 void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate,
@@ -1028,11 +1095,18 @@ void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream
   const size_t lds = adjoint_lds(g);
   const float* pm = b.p_max;
   const DevScalars* sc = b.sc;
-  if (MM <= 2) hipLaunchKernelGGL(k_adjoint<2>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
-  else if (MM <= 3) hipLaunchKernelGGL(k_adjoint<3>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
-  else if (MM <= 4) hipLaunchKernelGGL(k_adjoint<4>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
-  else if (MM <= 8) hipLaunchKernelGGL(k_adjoint<8>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
-  else hipLaunchKernelGGL(k_adjoint<0>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate);
+#define LFSR_ADJ(M) hipLaunchKernelGGL(k_adjoint<M>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate)
+  switch (MM) {
+    case 1: LFSR_ADJ(1); break;
+    case 2: LFSR_ADJ(2); break;
+    case 3: LFSR_ADJ(3); break;
+    case 4: LFSR_ADJ(4); break;
+    case 5: LFSR_ADJ(5); break;
+    case 6: LFSR_ADJ(6); break;
+    case 7: LFSR_ADJ(7); break;
+    default: LFSR_ADJ(0); break;
+  }
+#undef LFSR_ADJ
 }
 
 int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b) {

@@ -23,8 +23,10 @@ LFSR_NSTAT = 6
 EXPORTS = [
     "lfsr_workspace_bytes", "lfsr_create", "lfsr_destroy", "lfsr_last_error", "lfsr_solve", "lfsr_init",
     "lfsr_iterate", "lfsr_read_state", "lfsr_write_state", "lfsr_get_stats", "lfsr_forward", "lfsr_adjoint",
-    "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic",
+    "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic", "lfsr_profile_begin", "lfsr_profile_end",
 ]
+LFSR_K_FORWARD, LFSR_K_ADJOINT, LFSR_K_NLTV, LFSR_K_NORMAL, LFSR_K_CG, LFSR_K_OTHER, LFSR_K_COUNT = range(7)
+KERNEL_KINDS = ["forward", "adjoint", "nltv", "normal", "cg", "other"]
 
 
 class lfsr_params(ctypes.Structure):
@@ -98,6 +100,10 @@ def load():
     lib.lfsr_edge_weight.restype = I
     lib.lfsr_bicubic.argtypes = [H, F, F, V]
     lib.lfsr_bicubic.restype = I
+    lib.lfsr_profile_begin.argtypes = [H, ctypes.c_uint32, I]
+    lib.lfsr_profile_begin.restype = I
+    lib.lfsr_profile_end.argtypes = [H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.lfsr_profile_end.restype = I
     _lib = lib
     return lib
 
@@ -252,6 +258,20 @@ class Solver:
         out = self._empty(self.H, self.W) if out is None else out
         self._check(self.lib.lfsr_bicubic(self.handle, _ptr(lr_view), _ptr(out), _stream(stream)), self.handle)
         return out
+
+
+    def lfsr_profile_begin(self, kinds=None, capacity=8192):
+        mask = 0
+        for k in (kinds if kinds is not None else range(LFSR_K_COUNT)):
+            mask |= 1 << k
+        self._check(self.lib.lfsr_profile_begin(self.handle, mask, int(capacity)), self.handle)
+
+    def lfsr_profile_end(self):
+        """{kind name: (total ms, timed launches)}"""
+        tot = (ctypes.c_double * LFSR_K_COUNT)()
+        cnt = (ctypes.c_int32 * LFSR_K_COUNT)()
+        self._check(self.lib.lfsr_profile_end(self.handle, tot, cnt), self.handle)
+        return {KERNEL_KINDS[k]: (tot[k], cnt[k]) for k in range(LFSR_K_COUNT)}
 
 
 def disp_bound_for(disp, margin=1.0) -> float:

@@ -1,0 +1,136 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (same parameters, same kernels):
+
+* c2 (5x5 views, 512^2, x2, 50 ADMM iterations): the whole HR result against
+  the stored FP64 oracle solve, relative L2 <= 1e-4;
+* c3 (9x9 views, 1152^2, x3, 100 iterations): the result on 65536 seeded
+  pixels against the stored oracle solve, relative L2 <= 1e-4 on the samples;
+* c3 single operators and one ADMM iteration against the oracle computed
+  here (the duals and the weight map are local, so every element is checked).
+
+The stored values come from tests/golden/make_golden.py (oracle only); the
+inputs are regenerated here and their hashes must match the stored ones.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from helpers import rel_err  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2206_05047_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lfsr():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2206_05047_amd import lfsr as mod
+    mod.load()
+    return mod
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+
+
+def _n(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+_cache = {}
+
+
+def _case(name):
+    if name not in _cache:
+        print(f"[inputs {name}]", flush=True)
+        cfg = synth.config(name)
+        o = oracle.Oracle(cfg)
+        sc = synth.make_scene(cfg)
+        y = synth.degrade(o.forward(sc["x_gt"], sc["disp"]), synth.make_noise(cfg))
+        _cache[name] = dict(cfg=cfg, o=o, sc=sc, y=y)
+    return _cache[name]
+
+
+def _golden(name, c):
+    path = os.path.join(GOLDEN, f"solve_{name}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    g = np.load(path, allow_pickle=False)
+    assert str(g["y_sha256"]) == _sha(c["y"]), "regenerated LR views differ from the stored ones"
+    assert str(g["disp_sha256"]) == _sha(c["sc"]["disp"]), "regenerated disparity differs"
+    return g
+
+
+def _solver(lfsr, c):
+    bound = float(np.abs(c["sc"]["disp"]).max())
+    return lfsr.Solver(lfsr.make_params(c["cfg"], disp_bound=bound))
+
+
+def test_c2_full_solve_matches_stored_oracle(lfsr):
+    c = _case("c2")
+    g = _golden("c2", c)
+    s = _solver(lfsr, c)
+    x, st = s.lfsr_solve(_t(c["y"]), _t(c["sc"]["disp"]))
+    err = synth.rel_l2(_n(x), g["x"])
+    print(f"c2 rel_l2={err:.3e}", flush=True)
+    assert err < 1e-4
+    assert st["iters_run"] == c["cfg"]["n_iter"]
+    np.testing.assert_allclose(st["hist"][:, 0], g["hist"][:, 0], rtol=1e-4)
+
+
+def test_c3_full_solve_matches_stored_oracle_on_samples(lfsr):
+    c = _case("c3")
+    g = _golden("c3", c)
+    s = _solver(lfsr, c)
+    x, st = s.lfsr_solve(_t(c["y"]), _t(c["sc"]["disp"]))
+    xs = _n(x).ravel()[g["idx"]]
+    err = synth.rel_l2(xs, g["x_samples"])
+    print(f"c3 rel_l2(samples)={err:.3e} psnr={synth.psnr(_n(x), c['sc']['x_gt']):.3f} "
+          f"(oracle {float(g['psnr_gt']):.3f})", flush=True)
+    assert err < 1e-4
+    assert abs(np.linalg.norm(_n(x)) - float(g["norm"])) < 1e-4 * float(g["norm"])
+    np.testing.assert_allclose(st["hist"][:, 0], g["hist"][:, 0], rtol=1e-4)
+
+
+def test_c3_operators_match_oracle(lfsr):
+    c = _case("c3")
+    s = _solver(lfsr, c)
+    o, d = c["o"], c["sc"]["disp"]
+    rng = np.random.default_rng(31)
+    x = rng.uniform(0, 1, o.hr_shape).astype(np.float32)
+    e = rng.standard_normal(o.lr_shape).astype(np.float32)
+    t_gpu = _n(s.lfsr_forward(_t(x), _t(d)))
+    assert rel_err(t_gpu, o.forward(x, d)) < 2e-5
+    a_gpu = _n(s.lfsr_adjoint(_t(e), _t(d)))
+    assert rel_err(a_gpu, o.adjoint(e, d)) < 2e-5
+    # the GPU pair is adjoint to FP32 accuracy: <A x, e> = <x, A^T e>
+    lhs, rhs = np.vdot(t_gpu, e), np.vdot(x, a_gpu)
+    assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.vdot(t_gpu, t_gpu) * np.vdot(e, e))
+
+
+def test_c3_one_iteration_matches_oracle(lfsr):
+    c = _case("c3")
+    s = _solver(lfsr, c)
+    o, d, y = c["o"], c["sc"]["disp"], c["y"]
+    s.lfsr_init(_t(y), _t(d))
+    s.lfsr_iterate(1)
+    st = s.lfsr_read_state()
+    ref = o.init_state(y)
+    o.iterate(ref, y, d, count=1)
+    assert rel_err(_n(st["m"]), ref["m"]) < 2e-5
+    assert rel_err(_n(st["wD"]), ref["wD"]) < 2e-5
+    assert rel_err(_n(st["wS"]), ref["wS"]) < 2e-5
+    assert synth.rel_l2(_n(st["x"]), ref["x"]) < 1e-5
