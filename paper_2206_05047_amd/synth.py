@@ -21,9 +21,14 @@ from scipy import ndimage
 
 # Workload definitions.  Shapes follow the three plain-method workloads; the
 # free model parameters (lambda1, lambda2, vartheta, sigma_s, sigma_e), which
-# the paper does not publish, were fixed once by a coarse PSNR sweep of the
-# FP64 reference on the small workload and are frozen here.
-_COMMON = dict(lambda1=4.0, lambda2=2.0, theta=0.25, sigma_s=1.0, sigma_e=1.0,
+# the paper does not publish, were fixed by a sweep over all three workloads
+# that required the cost J to decrease monotonically over N and 2N
+# iterations and a rounding-level perturbation of the LR views to stay at
+# rounding level after N iterations, then took the best PSNR among those
+# settings; they are frozen here.  (Small penalties, e.g. vartheta = 1/4, make
+# the reweighted iteration with K = 5 CG steps drift away after some tens of
+# iterations on the larger workloads.)
+_COMMON = dict(lambda1=4.0, lambda2=2.0, theta=8.0, sigma_s=1.0, sigma_e=1.0,
                cg_iter=5, cg_tol=0.0, reweight=1, n_disp=1)
 
 CONFIGS = {
