@@ -70,6 +70,14 @@ typedef enum {
   LFSR_EBUSY = -6       /* reserved */
 } lfsr_status;
 
+/* Storage type of the solver state: the HR estimate x, the dual fields w_D
+ * and w_S, and the LR work stack (e in the wz-step, t = A p in CG).  With
+ * LFSR_F16 / LFSR_BF16 these are stored in 16 bits (rounded to nearest even
+ * at each store) and all stencil arithmetic stays FP32; x is kept as the
+ * 16-bit value the stencils read plus an FP32 remainder into which CG
+ * accumulates, so x is exact to FP32 and lfsr_read_state / lfsr_solve return
+ * that FP32 value.  The CG vectors r, p, Hp, the weight map and every
+ * reduction (FP64) are unchanged.  Inputs and outputs are always float. */
 typedef enum { LFSR_F32 = 0, LFSR_F16 = 1, LFSR_BF16 = 2 } lfsr_storage;
 
 typedef struct {
@@ -90,7 +98,7 @@ typedef struct {
   float cg_tol;               /* tau >= 0: CG continues while |r|^2 > tau (0: exactly K steps unless r = 0) */
   float stop_tol;             /* >= 0: stop after iteration n once res_n <= stop_tol * res_1 (0: run N) */
   float disp_bound;           /* > 0: the caller's bound on |disp| (sizes the warp halo; larger values are an input error) */
-  int32_t storage;            /* lfsr_storage of the dual fields and LR work buffers (LFSR_F32 only in this version) */
+  int32_t storage;            /* lfsr_storage of the solver state (see below) */
 } lfsr_params;
 
 #define LFSR_NSTAT 6
@@ -145,7 +153,9 @@ lfsr_status lfsr_read_state(lfsr_handle* h, float* d_x, float* d_wd, float* d_ws
 /* Replace the state (checkpoint resume): same layouts as lfsr_read_state;
  * n_done = iterations already run (decides whether the edge weight is
  * recomputed on the next iteration when reweight = 0).  All pointers
- * required except d_m when reweight = 1. */
+ * required except d_m when reweight = 1.  With 16-bit storage the duals are
+ * rounded to the storage type (exact for values lfsr_read_state returned)
+ * and x is split exactly, so read -> write -> iterate resumes bit for bit. */
 lfsr_status lfsr_write_state(lfsr_handle* h, const float* d_x, const float* d_wd, const float* d_ws,
                              const float* d_m, int32_t n_done, void* hip_stream);
 
@@ -159,7 +169,10 @@ lfsr_status lfsr_get_stats(lfsr_handle* h, lfsr_stats* out, void* hip_stream);
  *                 the scatter with the bilinear weights of W_k).
  *   lfsr_normal:  d_out = (lambda2 + vartheta*lambda1^2/2) A^T A d_p
  *                         + (vartheta/2) S^T S d_p with the weights of d_m
- *                 (the x-step normal operator G^T G of sec 5).
+ *                 (the x-step normal operator G^T G of sec 5); the
+ *                 intermediate A d_p is stored in the handle's storage type,
+ *                 exactly as in the solver's CG steps.
+ * lfsr_forward / lfsr_adjoint are FP32 throughout whatever the storage type.
  * They use the handle's work buffers, so they must not overlap an iteration. */
 lfsr_status lfsr_forward(lfsr_handle* h, const float* d_x, const float* d_disp, float* d_lr_out,
                          void* hip_stream);
@@ -196,6 +209,70 @@ typedef enum {
 
 lfsr_status lfsr_profile_begin(lfsr_handle* h, uint32_t kind_mask, int32_t capacity);
 lfsr_status lfsr_profile_end(lfsr_handle* h, double* h_total_ms, int32_t* h_launches);
+
+/* ------------------------------------------------------------------------
+ * Serving pool: many independent super-resolution jobs (any mix of angular
+ * sizes, spatial sizes and scales) solved concurrently on one GPU, each one
+ * the ADMM iteration of sec 5 (Algorithms 1 and 2) exactly as lfsr_solve
+ * runs it, so a job's result is bit-identical to its solo lfsr_solve.
+ *
+ * The caller gives the pool one device arena; a job is admitted when a slot
+ * is free and its workspace (lfsr_workspace_bytes of its parameters) fits in
+ * the arena's free space (first fit, 256-byte aligned), and its ADMM state
+ * stays resident there until it is harvested.  lfsr_pool_tick advances every
+ * active job by one ADMM iteration with a single launch of a HIP graph that
+ * holds one branch per job; the graph is captured again only when the set of
+ * active jobs has changed.  A job that has run its admm_iters iterations has
+ * its result copied to its d_hr_out on the pool's stream and is retired; a
+ * later lfsr_pool_poll reports it once the copy has completed and frees its
+ * arena space.  Jobs whose stop test fires idle (their iterations become
+ * no-ops on the device) until they reach admm_iters ticks.
+ *
+ * All input buffers of a job and its d_hr_out must stay valid until the job
+ * is reported by lfsr_pool_poll.  The pool's calls are not thread-safe.  A
+ * pool's work runs on an internal stream ordered after the caller's stream
+ * at each call (submit, tick) and before it at the end of each tick.
+ * ------------------------------------------------------------------------ */
+typedef struct lfsr_pool lfsr_pool;
+
+/* d_arena: device memory of `bytes` bytes (256-byte aligned, caller-owned,
+ * not freed by the pool); max_slots: 1..256 concurrent jobs. */
+lfsr_status lfsr_pool_create(void* d_arena, size_t bytes, int32_t max_slots, lfsr_pool** out);
+
+/* Waits for the pool's outstanding work, destroys every job and the pool.
+ * NULL-safe. */
+void lfsr_pool_destroy(lfsr_pool* pool);
+
+/* Text of the last error of this pool (thread-local text if pool is NULL). */
+const char* lfsr_pool_last_error(const lfsr_pool* pool);
+
+/* Admit a job: inputs as for lfsr_solve.  Returns LFSR_EBUSY (nothing done)
+ * when no slot is free or its workspace does not fit in the free arena space
+ * now; LFSR_ENOMEM when it can never fit (larger than the arena); LFSR_EINVAL
+ * for invalid parameters or NULL pointers.  On success *job_id receives the
+ * job's id (> 0) and the job's setup (input check, x0, w = 0) is enqueued,
+ * ordered after the work already on hip_stream.  Input errors of the job
+ * (non-finite values, |disp| > disp_bound) do not fail the call: the job
+ * runs and lfsr_pool_poll reports its status. */
+lfsr_status lfsr_pool_submit(lfsr_pool* pool, const lfsr_params* params, const float* d_lr, const float* d_disp,
+                             const float* d_occ, const float* d_x0, float* d_hr_out, void* hip_stream,
+                             int64_t* job_id);
+
+/* One ADMM iteration of every active job (one graph launch), then the
+ * retirement of the jobs that have finished.  hip_stream is ordered before
+ * and after the pool's work.  *h_active (may be NULL) receives the number of
+ * jobs advanced. */
+lfsr_status lfsr_pool_tick(lfsr_pool* pool, void* hip_stream, int32_t* h_active);
+
+/* Non-blocking harvest: up to `cap` ids of retired jobs whose result is
+ * complete in their d_hr_out, with their status (LFSR_OK, or the input error
+ * of lfsr_get_stats) and the number of ADMM iterations they ran. */
+lfsr_status lfsr_pool_poll(lfsr_pool* pool, int64_t* h_ids, int32_t* h_status, int32_t* h_iters, int32_t cap,
+                           int32_t* h_count);
+
+/* Occupancy: active and retiring jobs, free arena bytes, largest free block. */
+lfsr_status lfsr_pool_info(const lfsr_pool* pool, int32_t* h_active, int32_t* h_retiring, size_t* h_free,
+                           size_t* h_largest_free);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = [os.path.join(CSRC, "lfsr_kernels.hip"), os.path.join(CSRC, "lfsr_api.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lfsr_kernels.hip", "lfsr_api.hip", "lfsr_pool.hip")]
 OUT = os.path.join(HERE, "liblfsr.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

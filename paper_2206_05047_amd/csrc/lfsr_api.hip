@@ -8,21 +8,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lfsr.h"
-#include "lfsr_internal.h"
+#include "lfsr_handle.h"
 
 using namespace lfsr;
 
 namespace {
 
 thread_local std::string g_thread_err = "no error";
-
-struct Plan {
-  Geom g;
-  size_t off_x, off_m, off_vs, off_r, off_pv, off_hp, off_wd, off_ws0, off_ws1, off_lr, off_adj, off_pwzd,
-      off_ptv, off_prr0, off_prr1, off_pphp, off_pmax, off_stats, off_sc;
-  size_t bytes;
-};
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -115,7 +107,8 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   if (!(p->disp_bound > 0.f) || !std::isfinite(p->disp_bound) || p->disp_bound > 256.f)
     return fail(err, "disp_bound must be in (0, 256]");
   if (p->reweight != 0 && p->reweight != 1) return fail(err, "reweight must be 0 or 1");
-  if (p->storage != LFSR_F32) return fail(err, "only LFSR_F32 storage is supported in this version");
+  if (p->storage != LFSR_F32 && p->storage != LFSR_F16 && p->storage != LFSR_BF16)
+    return fail(err, "storage must be LFSR_F32, LFSR_F16 or LFSR_BF16");
 
   g.U = p->ang_rows;
   g.V = p->ang_cols;
@@ -186,8 +179,9 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   }
   if (!choose_tiles(g, err)) return false;
 
-  // workspace layout
+  // workspace layout; es = bytes per element of the storage type
   const size_t P = (size_t)g.p, Q = (size_t)g.q;
+  const size_t es = p->storage == LFSR_F32 ? 4 : 2;
   size_t o = 0;
   auto take = [&](size_t n) {
     size_t at = o;
@@ -195,16 +189,17 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
     return at;
   };
   pl->off_sc = take(sizeof(DevScalars));
-  pl->off_x = take(P * 4);
+  pl->off_x = take(P * es);
+  pl->off_dx = take(es == 4 ? 0 : P * 4);
   pl->off_m = take(P * 4);
   pl->off_vs = take(P * 4);
   pl->off_r = take(P * 4);
   pl->off_pv = take(P * 4);
   pl->off_hp = take(P * 4);
-  pl->off_wd = take((size_t)g.sk * Q * 4);
-  pl->off_ws0 = take((size_t)g.sd * P * 4);
-  pl->off_ws1 = take((size_t)g.sd * P * 4);
-  pl->off_lr = take((size_t)g.sk * Q * 4);
+  pl->off_wd = take((size_t)g.sk * Q * es);
+  pl->off_ws0 = take((size_t)g.sd * P * es);
+  pl->off_ws1 = take((size_t)g.sd * P * es);
+  pl->off_lr = take((size_t)g.sk * Q * es);
   pl->off_adj = take((size_t)g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4);
   {
     const dim3 fg = forward_grid(g), tg = tv_grid(g);
@@ -221,29 +216,6 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
 }
 
 }  // namespace
-
-struct Profile {
-  bool on = false;
-  uint32_t mask = 0;
-  std::vector<hipEvent_t> ev;  // pairs
-  std::vector<int> kind;
-  int used = 0;
-};
-
-struct lfsr_handle {
-  Profile prof;
-  lfsr_params prm;
-  Plan plan;
-  Bufs b;
-  char* ws;
-  int n_done;
-  bool bound;
-  bool broken;
-  const float* y;
-  const float* disp;
-  const float* occ;
-  std::string err;
-};
 
 namespace {
 
@@ -290,21 +262,22 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   const Geom& g = h->plan.g;
   const Bufs& b = h->b;
   // weights from x^(n-1) (sec 7.1: recomputed every iteration when reweighting)
-  timed(h, LFSR_K_OTHER, s, [&] { launch_edge(g, b.x, h->occ, b.m, s, b, kGateAdmm | kGateReweight); });
+  timed(h, LFSR_K_OTHER, s, [&] { launch_edge(g, b.x, b.st, h->occ, b.m, s, b, kGateAdmm | kGateReweight); });
   // z/w-steps of both blocks; e and the NLTV divergence feed v
-  timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_wzd(g, b.x, h->disp, h->y, s, b); });
+  timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_wzd(g, h->disp, h->y, s, b); });
   if (g.sd > 0) timed(h, LFSR_K_NLTV, s, [&] { launch_tv(g, s, b); });
-  timed(h, LFSR_K_ADJOINT, s, [&] { launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm, forward_blocks(g)); });
+  timed(h, LFSR_K_ADJOINT, s, [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm, forward_blocks(g)); });
   timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b); });
-  // x-step: K CG steps on G^T G delta = -v, accumulated straight into x
+  // x-step: K CG steps on G^T G delta = -v, accumulated straight into the FP32 estimate
   for (int k = 1; k <= h->prm.cg_iters; ++k) {
-    timed(h, LFSR_K_FORWARD, s, [&] { launch_forward(g, b.pv, h->disp, b.lr, s, b, kGateAdmm | kGateCg); });
+    timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_cg(g, b.pv, h->disp, s, b, kGateAdmm | kGateCg); });
     timed(h, LFSR_K_ADJOINT, s,
-          [&] { launch_adjoint(g, b.lr, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g)); });
+          [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g)); });
     timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgupd(g, k, s, b); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });
   }
+  if (b.st != kStF32) timed(h, LFSR_K_CG, s, [&] { launch_fold(g, s, b); });
   timed(h, LFSR_K_OTHER, s, [&] { launch_iter_end(g, s, b); });
   h->n_done += 1;
 }
@@ -341,16 +314,18 @@ lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, l
   h->ws = (char*)d_workspace;
   char* w = h->ws;
   h->b.sc = (DevScalars*)(w + pl.off_sc);
-  h->b.x = (float*)(w + pl.off_x);
+  h->b.st = p->storage;
+  h->b.x = w + pl.off_x;
+  h->b.dx = p->storage == LFSR_F32 ? nullptr : (float*)(w + pl.off_dx);
   h->b.m = (float*)(w + pl.off_m);
   h->b.vs = (float*)(w + pl.off_vs);
   h->b.r = (float*)(w + pl.off_r);
   h->b.pv = (float*)(w + pl.off_pv);
   h->b.hp = (float*)(w + pl.off_hp);
-  h->b.wD = (float*)(w + pl.off_wd);
-  h->b.wS[0] = (float*)(w + pl.off_ws0);
-  h->b.wS[1] = (float*)(w + pl.off_ws1);
-  h->b.lr = (float*)(w + pl.off_lr);
+  h->b.wD = w + pl.off_wd;
+  h->b.wS[0] = w + pl.off_ws0;
+  h->b.wS[1] = w + pl.off_ws1;
+  h->b.lr = w + pl.off_lr;
   h->b.adj = (float*)(w + pl.off_adj);
   h->b.p_wzd = (double*)(w + pl.off_pwzd);
   h->b.p_tv = (double*)(w + pl.off_ptv);
@@ -387,15 +362,18 @@ lfsr_status lfsr_init(lfsr_handle* h, const float* d_lr, const float* d_disp, co
   h->occ = d_occ;
   launch_reset(0, s, h->b);
   launch_check(g, d_lr, d_disp, d_occ, s, h->b);
-  launch_fill(h->b.wD, (long long)g.sk * g.q, 0.f, s);
-  launch_fill(h->b.wS[0], (long long)g.sd * g.p, 0.f, s);
+  launch_zero(h->b.wD, h->b.st, (long long)g.sk * g.q, s);
+  launch_zero(h->b.wS[0], h->b.st, (long long)g.sd * g.p, s);
   launch_fill(h->b.m, g.p, 1.f, s);
+  // x0 in FP32 (into x, or into the remainder buffer and then split)
+  float* x32 = h->b.st == kStF32 ? (float*)h->b.x : h->b.dx;
   if (d_x0) {
-    if (hipMemcpyAsync(h->b.x, d_x0, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(x32, d_x0, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
       return check_hip(h, "lfsr_init copy x0");
   } else {
-    launch_bicubic(g, d_lr + (size_t)g.kref * g.q, h->b.x, s);
+    launch_bicubic(g, d_lr + (size_t)g.kref * g.q, x32, s);
   }
+  if (h->b.st != kStF32) launch_split(g, x32, s, h->b);
   h->n_done = 0;
   h->bound = true;
   return check_hip(h, "lfsr_init");
@@ -416,10 +394,15 @@ lfsr_status lfsr_read_state(lfsr_handle* h, float* d_x, float* d_wd, float* d_ws
   if (st) return st;
   const Geom& g = h->plan.g;
   hipStream_t s = S(hip_stream);
-  if (d_x && hipMemcpyAsync(d_x, h->b.x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return check_hip(h, "lfsr_read_state x");
-  if (d_wd && hipMemcpyAsync(d_wd, h->b.wD, (size_t)g.sk * g.q * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return check_hip(h, "lfsr_read_state w_D");
+  if (h->b.st == kStF32) {
+    if (d_x && hipMemcpyAsync(d_x, h->b.x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return check_hip(h, "lfsr_read_state x");
+    if (d_wd && hipMemcpyAsync(d_wd, h->b.wD, (size_t)g.sk * g.q * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return check_hip(h, "lfsr_read_state w_D");
+  } else {
+    if (d_x) launch_join(g, d_x, s, h->b);
+    if (d_wd) launch_to_float(h->b.wD, h->b.st, d_wd, (long long)g.sk * g.q, s);
+  }
   if (d_ws) launch_copy_ws(d_ws, (long long)g.sd * g.p, s, h->b);
   if (d_m && hipMemcpyAsync(d_m, h->b.m, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return check_hip(h, "lfsr_read_state m");
@@ -437,11 +420,19 @@ lfsr_status lfsr_write_state(lfsr_handle* h, const float* d_x, const float* d_wd
   if (!h->y) return set_err(h, LFSR_ESTATE, "lfsr_write_state needs inputs bound by lfsr_init first");
   hipStream_t s = S(hip_stream);
   launch_reset(n_done, s, h->b);
-  if (hipMemcpyAsync(h->b.x, d_x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      hipMemcpyAsync(h->b.wD, d_wd, (size_t)g.sk * g.q * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-      (g.sd > 0 && hipMemcpyAsync(h->b.wS[0], d_ws, (size_t)g.sd * g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess) ||
-      (d_m && hipMemcpyAsync(h->b.m, d_m, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess))
-    return check_hip(h, "lfsr_write_state copy");
+  if (h->b.st == kStF32) {
+    if (hipMemcpyAsync(h->b.x, d_x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->b.wD, d_wd, (size_t)g.sk * g.q * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        (g.sd > 0 &&
+         hipMemcpyAsync(h->b.wS[0], d_ws, (size_t)g.sd * g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess))
+      return check_hip(h, "lfsr_write_state copy");
+  } else {  // x splits exactly; the duals round to the storage type
+    launch_split(g, d_x, s, h->b);
+    launch_from_float(d_wd, h->b.wD, h->b.st, (long long)g.sk * g.q, s);
+    if (g.sd > 0) launch_from_float(d_ws, h->b.wS[0], h->b.st, (long long)g.sd * g.p, s);
+  }
+  if (d_m && hipMemcpyAsync(h->b.m, d_m, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return check_hip(h, "lfsr_write_state copy m");
   h->n_done = n_done;
   h->bound = true;
   return check_hip(h, "lfsr_write_state");
@@ -488,8 +479,10 @@ lfsr_status lfsr_solve(lfsr_handle* h, const float* d_lr, const float* d_disp, c
   if (st) return st;
   st = lfsr_iterate(h, h->prm.admm_iters, hip_stream);
   if (st) return st;
-  if (hipMemcpyAsync(d_hr_out, h->b.x, (size_t)h->plan.g.p * 4, hipMemcpyDeviceToDevice, S(hip_stream)) !=
-      hipSuccess)
+  if (h->b.st != kStF32)
+    launch_join(h->plan.g, d_hr_out, S(hip_stream), h->b);
+  else if (hipMemcpyAsync(d_hr_out, h->b.x, (size_t)h->plan.g.p * 4, hipMemcpyDeviceToDevice, S(hip_stream)) !=
+           hipSuccess)
     return check_hip(h, "lfsr_solve copy out");
   if (h_stats) return lfsr_get_stats(h, h_stats, hip_stream);
   return check_hip(h, "lfsr_solve");
@@ -509,7 +502,7 @@ lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp,
   if (!d_lr || !d_disp || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
   const Geom& g = h->plan.g;
   const int npmax = launch_absmax(g, d_lr, (long long)g.sk * g.q, S(hip_stream), h->b);
-  launch_adjoint(g, d_lr, d_disp, S(hip_stream), h->b, 0, npmax);
+  launch_adjoint(g, d_lr, kStF32, d_disp, S(hip_stream), h->b, 0, npmax);
   launch_merge(g, d_hr_out, S(hip_stream), h->b);
   return check_hip(h, "lfsr_adjoint");
 }
@@ -521,8 +514,8 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   if (!d_p || !d_disp || !d_m || !d_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
   const Geom& g = h->plan.g;
   hipStream_t s = S(hip_stream);
-  launch_forward(g, d_p, d_disp, h->b.lr, s, h->b, 0);
-  launch_adjoint(g, h->b.lr, d_disp, s, h->b, 0, forward_blocks(g));
+  launch_forward_cg(g, d_p, d_disp, s, h->b, 0);
+  launch_adjoint(g, h->b.lr, h->b.st, d_disp, s, h->b, 0, forward_blocks(g));
   launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0);
   return check_hip(h, "lfsr_normal");
 }
@@ -531,7 +524,7 @@ lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_oc
   lfsr_status st = usable(h);
   if (st) return st;
   if (!d_x || !d_m_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
-  launch_edge(h->plan.g, d_x, d_occ, d_m_out, S(hip_stream), h->b, 0);
+  launch_edge(h->plan.g, d_x, kStF32, d_occ, d_m_out, S(hip_stream), h->b, 0);
   return check_hip(h, "lfsr_edge_weight");
 }
 

@@ -70,17 +70,23 @@ struct DevScalars {
   int err_flags;    // bit 0: non-finite input, bit 1: |disp| > disp_bound
 };
 
-// Device pointers of one handle's working set.
+// Storage element types of the solver state (the values of lfsr_storage).
+enum : int { kStF32 = 0, kStF16 = 1, kStBF16 = 2 };
+
+// Device pointers of one handle's working set.  x, wD, wS and lr hold
+// elements of the storage type `st`; everything else is float / double.
 struct Bufs {
-  float* x;        // [H][W] HR estimate
+  int st;          // storage type of x, wD, wS, lr
+  void* x;         // [H][W] HR estimate (16-bit storage: the rounded part)
+  float* dx;       // [H][W] 16-bit storage only: FP32 remainder, x = x16 + dx; CG accumulates here
   float* m;        // [H][W] weight map w_e * occ
   float* vs;       // [H][W] NLTV divergence part of v
   float* r;        // [H][W] CG residual
   float* pv;       // [H][W] CG direction
   float* hp;       // [H][W] H p
-  float* wD;       // [sk][sy][sx] data dual
-  float* wS[2];    // [sd][H][W] NLTV dual, ping-pong
-  float* lr;       // [sk][sy][sx] e (wz-step) or t = A p (CG)
+  void* wD;        // [sk][sy][sx] data dual
+  void* wS[2];     // [sd][H][W] NLTV dual, ping-pong
+  void* lr;        // [sk][sy][sx] e (wz-step) or t = A p (CG)
   float* adj;      // [a_nty*a_ntx][a_ey][a_ex] per-tile adjoint partial images
   double* p_wzd;   // [forward blocks][3] data-block partial sums
   double* p_tv;    // [tv blocks][2] NLTV-block partial sums
@@ -107,14 +113,18 @@ bool adjoint_tile_ok(const Geom& g);
 dim3 forward_grid(const Geom& g);
 dim3 adjoint_grid(const Geom& g);
 dim3 tv_grid(const Geom& g);
+// FP32 operator: out = A src
 void launch_forward(const Geom& g, const float* src, const float* disp, float* out, hipStream_t s,
                     const Bufs& b, int gate);
-void launch_forward_wzd(const Geom& g, const float* src, const float* disp, const float* y, hipStream_t s,
-                        const Bufs& b);
-// npmax: number of per-block maxima of |lr| in b.p_max (forward_blocks(g)
-// after a forward launch, or the return value of launch_absmax)
-void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate,
-                    int npmax);
+// CG product: b.lr (storage type) = A src
+void launch_forward_cg(const Geom& g, const float* src, const float* disp, hipStream_t s, const Bufs& b, int gate);
+// data-block wz-step from b.x: b.lr = e, b.wD updated
+void launch_forward_wzd(const Geom& g, const float* disp, const float* y, hipStream_t s, const Bufs& b);
+// lr holds elements of storage type lr_st.  npmax: number of per-block
+// maxima of |lr| in b.p_max (forward_blocks(g) after a forward launch, or
+// the return value of launch_absmax)
+void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp, hipStream_t s, const Bufs& b,
+                    int gate, int npmax);
 int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b);
 int forward_blocks(const Geom& g);
 void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b);
@@ -125,7 +135,14 @@ void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b);
 void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b);
 void launch_cgp(const Geom& g, int step, hipStream_t s, const Bufs& b);
 void launch_iter_end(const Geom& g, hipStream_t s, const Bufs& b);
-void launch_edge(const Geom& g, const float* x, const float* occ, float* m, hipStream_t s, const Bufs& b, int gate);
+void launch_edge(const Geom& g, const void* x, int x_st, const float* occ, float* m, hipStream_t s, const Bufs& b,
+                 int gate);
+void launch_fold(const Geom& g, hipStream_t s, const Bufs& b);                     // x16 + dx -> x16, dx
+void launch_split(const Geom& g, const float* src, hipStream_t s, const Bufs& b);  // src -> x16, dx
+void launch_join(const Geom& g, float* out, hipStream_t s, const Bufs& b);         // x16 + dx -> out
+void launch_to_float(const void* in, int st, float* out, long long n, hipStream_t s);
+void launch_from_float(const float* in, void* out, int st, long long n, hipStream_t s);
+void launch_zero(void* p, int st, long long n, hipStream_t s);
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s);
 void launch_check(const Geom& g, const float* y, const float* disp, const float* occ, hipStream_t s, const Bufs& b);
 void launch_fill(float* p, long long n, float v, hipStream_t s);

@@ -25,6 +25,8 @@
 //    fence writes back the whole L2 of the XCD.  Control scalars (CG alpha,
 //    beta, pi, stop flags) stay on the device: an ADMM iteration never waits
 //    for the host.
+#include <type_traits>
+
 #include "lfsr_internal.h"
 
 namespace lfsr {
@@ -87,8 +89,8 @@ __device__ __forceinline__ double* stats_row(const Geom& g, double* stats, const
 // outside [0,H) x [0,W)), into dst[r * ld + c].  Every thread issues a batch
 // of loads (clamped, always in-bounds addresses) before any LDS store, so the
 // global-memory latency is paid once per batch rather than once per element.
-template <int BATCH = 8>
-__device__ __forceinline__ void stage_tile(float* __restrict__ dst, int ld, const float* __restrict__ src, int H, int W,
+template <typename TS, int BATCH = 8>
+__device__ __forceinline__ void stage_tile(float* __restrict__ dst, int ld, const TS* __restrict__ src, int H, int W,
                                            int Y0, int X0, int rows, int cols) {
   const int n = rows * cols;
   const float inv = 1.f / (float)cols;  // (e + 1/2)/cols in float floors exactly for e < 2^16, cols < 400
@@ -102,7 +104,7 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ dst, int ld, cons
       const int Y = Y0 + r, X = X0 + c;
       const bool ok = e < n && Y >= 0 && Y < H && X >= 0 && X < W;
       const int Yc = min(max(Y, 0), H - 1), Xc = min(max(X, 0), W - 1);
-      const float t = src[(size_t)Yc * W + Xc];
+      const float t = (float)src[(size_t)Yc * W + Xc];
       v[j] = ok ? t : 0.f;
       off[j] = e < n ? r * ld + c : -1;
     }
@@ -143,10 +145,13 @@ __device__ __forceinline__ float adj_merge(const Geom& g, const float* __restric
 // A^T, e = lambda2 r + (vartheta/2) lambda1 (2 w_D' - w_D), written to `out`;
 // per-block partials {sum|r|, sum r^2, sum (w_D'-w_D)^2} go to `part`.
 // grid = (ceil(sx/f_tlx), ceil(sy/f_tly), ceil(sk/f_vpb)).
-template <bool WZD, int KBT>  // KBT: compile-time blur size (0: runtime g.kb)
-__global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __restrict__ src,
-                                                      const float* __restrict__ disp, float* __restrict__ out,
-                                                      const float* __restrict__ y, float* __restrict__ wD,
+// TS is the element type of `src`, TO that of `out` and `wD` (float, or a
+// 16-bit storage type: values are rounded once, at the store; all arithmetic
+// is FP32).  `pmax` receives per-block max |out| of the stored values.
+template <bool WZD, int KBT, typename TS, typename TO>  // KBT: compile-time blur size (0: runtime g.kb)
+__global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restrict__ src,
+                                                      const float* __restrict__ disp, TO* __restrict__ out,
+                                                      const float* __restrict__ y, TO* __restrict__ wD,
                                                       double* __restrict__ part, float* __restrict__ pmax,
                                                       const DevScalars* __restrict__ sc, int gate) {
   if (gated(sc, g, gate)) return;
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
     float yv = 0.f, w0 = 0.f;
     if (WZD && vout) {  // issued early; consumed after the two LDS passes
       yv = y[o];
-      w0 = wD[o];
+      w0 = (float)wD[o];
     }
     // W_k at every blur position of this thread: all gathers, then all stores
     float val[kFwdSlots];
@@ -272,15 +277,17 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
         t = fmaf(g.g[a], hb[voff + a * tlx], t);
       }
       if constexpr (!WZD) {
-        out[o] = t;
-        vmax = fmaxf(vmax, fabsf(t));
+        const TO ts = (TO)t;
+        out[o] = ts;
+        vmax = fmaxf(vmax, fabsf((float)ts));
       } else {
         const float r = t - yv;
         const float wn = clipf(fmaf(g.lambda1, r, w0), g.clip);
         const float e = g.lambda2 * r + g.half_theta * g.lambda1 * (2.f * wn - w0);
-        out[o] = e;
-        vmax = fmaxf(vmax, fabsf(e));
-        wD[o] = wn;
+        const TO es = (TO)e;
+        out[o] = es;
+        vmax = fmaxf(vmax, fabsf((float)es));
+        wD[o] = (TO)wn;
         const double rd = (double)r, dw = (double)wn - (double)w0;
         s_abs += fabs(rd);
         s_sq += rd * rd;
@@ -328,8 +335,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const float* __res
 // saturation (resolution 2^-29 M per contribution) and at most
 // sk*(2 halo + 1)^2 contributions per cell stay far below 2^63.  M comes from
 // the producer's per-block maxima (`pmax`, npmax of them).
-template <int MMT>  // compile-time taps per polyphase phase, exactly (2 rb)/zeta + 1 (0: runtime, taps in LDS)
-__global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __restrict__ lr,
+// TI is the element type of `lr` (float or a 16-bit storage type).
+template <int MMT, typename TI>  // MMT: compile-time taps per polyphase phase, exactly (2 rb)/zeta + 1 (0: runtime)
+__global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restrict__ lr,
                                                       const float* __restrict__ disp, float* __restrict__ outp,
                                                       const float* __restrict__ pmax, int npmax,
                                                       const DevScalars* __restrict__ sc, int gate) {
@@ -420,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
   float ereg[kAdjESlots];
 #pragma unroll
   for (int s = 0; s < kAdjESlots; ++s) {
-    const float t = lr[eoff[s] >= 0 ? eoff[s] : 0];
+    const float t = (float)lr[eoff[s] >= 0 ? eoff[s] : 0];
     ereg[s] = eoff[s] >= 0 ? t : 0.f;
   }
   __syncthreads();  // accumulator zeroed, taps ready
@@ -451,10 +459,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const float* __res
       if (idx < RL * LX) e_[idx] = ereg[s];
     }
     if (k + 1 < g.sk) {  // prefetch the next view's LR rows
-      const float* ln = lr + (size_t)(k + 1) * g.q;
+      const TI* ln = lr + (size_t)(k + 1) * g.q;
 #pragma unroll
       for (int s = 0; s < kAdjESlots; ++s) {
-        const float t = ln[eoff[s] >= 0 ? eoff[s] : 0];
+        const float t = (float)ln[eoff[s] >= 0 ? eoff[s] : 0];
         ereg[s] = eoff[s] >= 0 ? t : 0.f;
       }
     }
@@ -561,9 +569,9 @@ __global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restr
 // The second term is pulled: f_d(z-d) is recomputed from the previous dual,
 // which ping-pong buffers keep intact.  Per-block partials {sum|g|,
 // sum (w_S'-w_S)^2} go to `part`.  grid = (ceil(W/64), ceil(H/16)).
-template <bool INTERIOR>
+template <bool INTERIOR, typename T>
 __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__ xs, const float* __restrict__ ms,
-                                        const float* wo, float* wn_, float* __restrict__ vs, int X0, int Y0,
+                                        const T* wo, T* wn_, float* __restrict__ vs, int X0, int Y0,
                                         double& s_abs, double& s_dw) {
   const int rw = g.rw;
   const int LXd = kTvTileX + 2 * rw;
@@ -583,13 +591,13 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
   float c0[4], c2[4], n0[4], n2[4];
   auto load = [&](int d, float (&w0)[4], float (&w2)[4]) {
     const int dy = g.ody[d], dx = g.odx[d];
-    const float* wd = wo + (size_t)d * g.p;
+    const T* wd = wo + (size_t)d * g.p;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const size_t o = (size_t)Y[rr] * g.W + X;
-      w0[rr] = in[rr] ? wd[o] : 0.f;
+      w0[rr] = in[rr] ? (float)wd[o] : 0.f;
       const bool bin = INTERIOR || (in[rr] && Y[rr] - dy >= 0 && Y[rr] - dy < g.H && X - dx >= 0 && X - dx < g.W);
-      w2[rr] = bin ? wd[o - (ptrdiff_t)dy * g.W - dx] : 0.f;
+      w2[rr] = bin ? (float)wd[o - (ptrdiff_t)dy * g.W - dx] : 0.f;
     }
   };
   if (g.sd > 0) load(0, c0, c2);
@@ -607,7 +615,7 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     const int dy = g.ody[d], dx = g.odx[d];
     const int dd = dy * LXd + dx;
     const float c = g.cd[d];
-    float* wnd = wn_ + (size_t)d * g.p;
+    T* wnd = wn_ + (size_t)d * g.p;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       if (!in[rr]) continue;
@@ -615,7 +623,7 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
       const bool fin = INTERIOR || (Y[rr] + dy >= 0 && Y[rr] + dy < g.H && X + dx >= 0 && X + dx < g.W);
       const float gv = fin ? c * mz * (xz - xs[sl[rr] + dd]) : 0.f;
       const float wn = clipf(gv + w0[rr], g.clip);
-      wnd[(size_t)Y[rr] * g.W + X] = wn;
+      wnd[(size_t)Y[rr] * g.W + X] = (T)wn;
       if (fin) acc[rr] = fmaf(c * mz, 2.f * wn - w0[rr], acc[rr]);
       const double dw = (double)wn - (double)w0[rr];
       s_abs += fabs((double)gv);
@@ -634,8 +642,11 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     if (in[rr]) vs[(size_t)Y[rr] * g.W + X] = acc[rr];
 }
 
-__global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict__ x, const float* __restrict__ m,
-                                                 float* ws0, float* ws1, float* __restrict__ vs,
+// T: storage type of x and of the dual; the dual recomputed for the pulled
+// term is the same FP32 value the owning thread stores (rounded) for w_S'.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
+                                                 T* ws0, T* ws1, float* __restrict__ vs,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
   extern __shared__ float smem[];
@@ -647,12 +658,12 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const float* __restrict
   stage_tile(xs, LXd, x, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
   stage_tile(ms, LXd, m, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
   __syncthreads();
-  const float* wo = sc->wcur ? ws1 : ws0;
-  float* wn_ = sc->wcur ? ws0 : ws1;
+  const T* wo = sc->wcur ? ws1 : ws0;
+  T* wn_ = sc->wcur ? ws0 : ws1;
   const bool interior = X0 - rw >= 0 && X0 + kTvTileX + rw <= g.W && Y0 - rw >= 0 && Y0 + kTvTileY + rw <= g.H;
   double s_abs = 0.0, s_dw = 0.0;
-  if (interior) tv_tile<true>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
-  else tv_tile<false>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  if (interior) tv_tile<true, T>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  else tv_tile<false, T>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
   double v[2] = {s_abs, s_dw};
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -789,7 +800,8 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
 }
 
 // CG step `step` (1-based), part 1: pi = <r,r> from the previous partials,
-// alpha = pi / <p, Hp>; x += alpha p (the x-step accumulates straight into x),
+// alpha = pi / <p, Hp>; x += alpha p (the x-step accumulates straight into the
+// FP32 estimate: x itself, or the FP32 remainder of a 16-bit x),
 // r -= alpha Hp, partials of the new <r, r>.  CG stops (Algorithm 2) when
 // pi <= tau, pi = 0, or <p, Hp> <= 0.
 __global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ x, float* __restrict__ r,
@@ -891,16 +903,17 @@ __global__ __launch_bounds__(kThreads) void k_iter_end(Geom g, const double* __r
 
 // ---------------------------------------------------------------------------
 // sec 3.4: m = exp(-|grad x|^2 / sigma_e) * occ, forward differences.
-__global__ __launch_bounds__(kThreads) void k_edge(Geom g, const float* __restrict__ x, const float* __restrict__ occ,
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_edge(Geom g, const T* __restrict__ x, const float* __restrict__ occ,
                                                    float* __restrict__ m, const DevScalars* __restrict__ sc, int gate) {
   if (gated(sc, g, gate)) return;
   for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
     const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
     float we = 1.f;
     if (g.use_edge) {
-      const float xz = x[o];
-      const float gx = X + 1 < g.W ? x[o + 1] - xz : 0.f;
-      const float gy = Y + 1 < g.H ? x[o + g.W] - xz : 0.f;
+      const float xz = (float)x[o];
+      const float gx = X + 1 < g.W ? (float)x[o + 1] - xz : 0.f;
+      const float gy = Y + 1 < g.H ? (float)x[o + g.W] - xz : 0.f;
       we = expf(-(gx * gx + gy * gy) * g.inv_sigma_e);
     }
     m[o] = occ ? we * occ[o] : we;
@@ -984,12 +997,64 @@ __global__ void k_reset(DevScalars* sc, int n_done) {
   sc->err_flags = 0;
 }
 
-// Copy the current NLTV dual (selected on the device) out.
-__global__ __launch_bounds__(kThreads) void k_copy_ws(const float* __restrict__ ws0, const float* __restrict__ ws1,
+// Copy the current NLTV dual (selected on the device) out as float.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_copy_ws(const T* __restrict__ ws0, const T* __restrict__ ws1,
                                                       float* __restrict__ out, long long n,
                                                       const DevScalars* __restrict__ sc) {
-  const float* s = sc->wcur ? ws1 : ws0;
-  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads) out[o] = s[o];
+  const T* s = sc->wcur ? ws1 : ws0;
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads)
+    out[o] = (float)s[o];
+}
+
+// Element-wise conversion between float and a storage type.
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kThreads) void k_convert(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads)
+    out[o] = (TO)(float)in[o];
+}
+
+// Split an FP32 image into a 16-bit part and its FP32 rounding remainder:
+// x16 = T(v), dx = v - x16 (exact), so x16 + dx reproduces v bit for bit.
+// `src` may alias `dx`.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_split(const float* src, T* __restrict__ x16, float* dx, long long n) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads) {
+    const float v = src[o];
+    const T t = (T)v;
+    x16[o] = t;
+    dx[o] = v - (float)t;
+  }
+}
+
+// End of a 16-bit x-step: fold the FP32 CG accumulation into the stored
+// estimate, keeping the new rounding remainder (no stagnation below the
+// 16-bit ulp).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fold(Geom g, T* __restrict__ x16, float* __restrict__ dx,
+                                                   const DevScalars* __restrict__ sc) {
+  if (sc->admm_done) return;
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
+    const float v = (float)x16[o] + dx[o];
+    const T t = (T)v;
+    x16[o] = t;
+    dx[o] = v - (float)t;
+  }
+}
+
+// FP32 estimate x16 + dx of a 16-bit x.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_join(const T* __restrict__ x16, const float* __restrict__ dx,
+                                                   float* __restrict__ out, long long n) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads)
+    out[o] = (float)x16[o] + dx[o];
+}
+
+// Zero n elements of a storage-typed buffer.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_zero(T* __restrict__ p, long long n) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads)
+    p[o] = (T)0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -1059,12 +1124,24 @@ dim3 tv_grid(const Geom& g) { return dim3((g.W + kTvTileX - 1) / kTvTileX, (g.H 
 
 static inline int nblocks(dim3 d) { return (int)(d.x * d.y * d.z); }
 
-template <bool WZD>
-static void launch_fwd_kb(const Geom& g, const float* src, const float* disp, float* out, const float* y, float* wD,
+// Calls f with a null pointer of the storage element type `st`.
+template <class F>
+static void by_storage(int st, F&& f) {
+  switch (st) {
+    case kStF16: f((_Float16*)nullptr); break;
+    case kStBF16: f((__bf16*)nullptr); break;
+    default: f((float*)nullptr); break;
+  }
+}
+#define LFSR_ELEM(tag) std::remove_pointer_t<decltype(tag)>
+
+template <bool WZD, typename TS, typename TO>
+static void launch_fwd_kb(const Geom& g, const TS* src, const float* disp, TO* out, const float* y, TO* wD,
                           double* part, float* pmax, const DevScalars* sc, int gate, hipStream_t s) {
   const dim3 grid = forward_grid(g), blk(kThreads);
   const size_t lds = forward_lds(g);
-#define LFSR_FWD(KB) hipLaunchKernelGGL((k_forward<WZD, KB>), grid, blk, lds, s, g, src, disp, out, y, wD, part, pmax, sc, gate)
+#define LFSR_FWD(KB) \
+  hipLaunchKernelGGL((k_forward<WZD, KB, TS, TO>), grid, blk, lds, s, g, src, disp, out, y, wD, part, pmax, sc, gate)
   switch (g.kb) {
     case 1: LFSR_FWD(1); break;
     case 3: LFSR_FWD(3); break;
@@ -1080,33 +1157,46 @@ static void launch_fwd_kb(const Geom& g, const float* src, const float* disp, fl
 
 void launch_forward(const Geom& g, const float* src, const float* disp, float* out, hipStream_t s,
                     const Bufs& b, int gate) {
-  launch_fwd_kb<false>(g, src, disp, out, nullptr, nullptr, nullptr, b.p_max, b.sc, gate, s);
+  launch_fwd_kb<false>(g, src, disp, out, (const float*)nullptr, (float*)nullptr, nullptr, b.p_max, b.sc, gate, s);
 }
 
-void launch_forward_wzd(const Geom& g, const float* src, const float* disp, const float* y, hipStream_t s,
-                        const Bufs& b) {
-  launch_fwd_kb<true>(g, src, disp, b.lr, y, b.wD, b.p_wzd, b.p_max, b.sc, (int)kGateAdmm, s);
+void launch_forward_cg(const Geom& g, const float* src, const float* disp, hipStream_t s, const Bufs& b, int gate) {
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    launch_fwd_kb<false>(g, src, disp, (T*)b.lr, (const float*)nullptr, (T*)nullptr, nullptr, b.p_max, b.sc, gate, s);
+  });
 }
 
-void launch_adjoint(const Geom& g, const float* lr, const float* disp, hipStream_t s, const Bufs& b, int gate,
-                    int npmax) {
+void launch_forward_wzd(const Geom& g, const float* disp, const float* y, hipStream_t s, const Bufs& b) {
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    launch_fwd_kb<true>(g, (const T*)b.x, disp, (T*)b.lr, y, (T*)b.wD, b.p_wzd, b.p_max, b.sc, (int)kGateAdmm, s);
+  });
+}
+
+void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp, hipStream_t s, const Bufs& b,
+                    int gate, int npmax) {
   const int MM = (2 * g.rb) / g.zeta + 1;
   const dim3 grid = adjoint_grid(g), blk(kThreads);
   const size_t lds = adjoint_lds(g);
   const float* pm = b.p_max;
   const DevScalars* sc = b.sc;
-#define LFSR_ADJ(M) hipLaunchKernelGGL(k_adjoint<M>, grid, blk, lds, s, g, lr, disp, b.adj, pm, npmax, sc, gate)
-  switch (MM) {
-    case 1: LFSR_ADJ(1); break;
-    case 2: LFSR_ADJ(2); break;
-    case 3: LFSR_ADJ(3); break;
-    case 4: LFSR_ADJ(4); break;
-    case 5: LFSR_ADJ(5); break;
-    case 6: LFSR_ADJ(6); break;
-    case 7: LFSR_ADJ(7); break;
-    default: LFSR_ADJ(0); break;
-  }
+  by_storage(lr_st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    const T* in = (const T*)lr;
+#define LFSR_ADJ(M) hipLaunchKernelGGL((k_adjoint<M, T>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, sc, gate)
+    switch (MM) {
+      case 1: LFSR_ADJ(1); break;
+      case 2: LFSR_ADJ(2); break;
+      case 3: LFSR_ADJ(3); break;
+      case 4: LFSR_ADJ(4); break;
+      case 5: LFSR_ADJ(5); break;
+      case 6: LFSR_ADJ(6); break;
+      case 7: LFSR_ADJ(7); break;
+      default: LFSR_ADJ(0); break;
+    }
 #undef LFSR_ADJ
+  });
 }
 
 int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b) {
@@ -1122,8 +1212,11 @@ void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b) {
 }
 
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_tv, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, (const float*)b.x, (const float*)b.m,
-                     b.wS[0], b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc);
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_tv<T>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m,
+                       (T*)b.wS[0], (T*)b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc);
+  });
 }
 
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
@@ -1139,7 +1232,8 @@ void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b) {
 }
 
 void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_cgupd, dim3(g.red_blocks), dim3(kThreads), 0, s, g, b.x, b.r, (const float*)b.pv,
+  float* xacc = b.st == kStF32 ? (float*)b.x : b.dx;
+  hipLaunchKernelGGL(k_cgupd, dim3(g.red_blocks), dim3(kThreads), 0, s, g, xacc, b.r, (const float*)b.pv,
                      (const float*)b.hp, (const double*)b.p_rr[(step - 1) & 1], b.p_rr[step & 1],
                      (const double*)b.p_php, nblocks(tv_grid(g)), step, b.sc);
 }
@@ -1155,8 +1249,60 @@ void launch_iter_end(const Geom& g, hipStream_t s, const Bufs& b) {
                      (const double*)b.p_rr[1], b.stats, b.sc);
 }
 
-void launch_edge(const Geom& g, const float* x, const float* occ, float* m, hipStream_t s, const Bufs& b, int gate) {
-  hipLaunchKernelGGL(k_edge, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, x, occ, m, (const DevScalars*)b.sc, gate);
+void launch_edge(const Geom& g, const void* x, int x_st, const float* occ, float* m, hipStream_t s, const Bufs& b,
+                 int gate) {
+  by_storage(x_st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_edge<T>, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, (const T*)x, occ, m,
+                       (const DevScalars*)b.sc, gate);
+  });
+}
+
+void launch_fold(const Geom& g, hipStream_t s, const Bufs& b) {
+  if (b.st == kStF32) return;
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_fold<T>, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, (T*)b.x, b.dx, (const DevScalars*)b.sc);
+  });
+}
+
+void launch_split(const Geom& g, const float* src, hipStream_t s, const Bufs& b) {
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_split<T>, dim3(grid1d(g.p)), dim3(kThreads), 0, s, src, (T*)b.x, b.dx, (long long)g.p);
+  });
+}
+
+void launch_join(const Geom& g, float* out, hipStream_t s, const Bufs& b) {
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_join<T>, dim3(grid1d(g.p)), dim3(kThreads), 0, s, (const T*)b.x, (const float*)b.dx, out,
+                       (long long)g.p);
+  });
+}
+
+void launch_to_float(const void* in, int st, float* out, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  by_storage(st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL((k_convert<T, float>), dim3(grid1d(n)), dim3(kThreads), 0, s, (const T*)in, out, n);
+  });
+}
+
+void launch_from_float(const float* in, void* out, int st, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  by_storage(st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL((k_convert<float, T>), dim3(grid1d(n)), dim3(kThreads), 0, s, in, (T*)out, n);
+  });
+}
+
+void launch_zero(void* p, int st, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  by_storage(st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_zero<T>, dim3(grid1d(n)), dim3(kThreads), 0, s, (T*)p, n);
+  });
 }
 
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s) {
@@ -1180,8 +1326,12 @@ void launch_reset(int n_done, hipStream_t s, const Bufs& b) {
 
 void launch_copy_ws(float* out, long long n, hipStream_t s, const Bufs& b) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_copy_ws, dim3(grid1d(n)), dim3(kThreads), 0, s, (const float*)b.wS[0],
-                     (const float*)b.wS[1], out, n, (const DevScalars*)b.sc);
+  by_storage(b.st, [&](auto* tag) {
+    using T = LFSR_ELEM(tag);
+    hipLaunchKernelGGL(k_copy_ws<T>, dim3(grid1d(n)), dim3(kThreads), 0, s, (const T*)b.wS[0], (const T*)b.wS[1],
+                       out, n, (const DevScalars*)b.sc);
+  });
 }
+#undef LFSR_ELEM
 
 }  // namespace lfsr

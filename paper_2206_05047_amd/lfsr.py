@@ -24,6 +24,8 @@ EXPORTS = [
     "lfsr_workspace_bytes", "lfsr_create", "lfsr_destroy", "lfsr_last_error", "lfsr_solve", "lfsr_init",
     "lfsr_iterate", "lfsr_read_state", "lfsr_write_state", "lfsr_get_stats", "lfsr_forward", "lfsr_adjoint",
     "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic", "lfsr_profile_begin", "lfsr_profile_end",
+    "lfsr_pool_create", "lfsr_pool_destroy", "lfsr_pool_last_error", "lfsr_pool_submit", "lfsr_pool_tick",
+    "lfsr_pool_poll", "lfsr_pool_info",
 ]
 LFSR_K_FORWARD, LFSR_K_ADJOINT, LFSR_K_NLTV, LFSR_K_NORMAL, LFSR_K_CG, LFSR_K_OTHER, LFSR_K_COUNT = range(7)
 KERNEL_KINDS = ["forward", "adjoint", "nltv", "normal", "cg", "other"]
@@ -104,6 +106,23 @@ def load():
     lib.lfsr_profile_begin.restype = I
     lib.lfsr_profile_end.argtypes = [H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
     lib.lfsr_profile_end.restype = I
+    PL = ctypes.c_void_p
+    lib.lfsr_pool_create.argtypes = [V, ctypes.c_size_t, I, ctypes.POINTER(PL)]
+    lib.lfsr_pool_create.restype = I
+    lib.lfsr_pool_destroy.argtypes = [PL]
+    lib.lfsr_pool_destroy.restype = None
+    lib.lfsr_pool_last_error.argtypes = [PL]
+    lib.lfsr_pool_last_error.restype = ctypes.c_char_p
+    lib.lfsr_pool_submit.argtypes = [PL, P, F, F, F, F, F, V, ctypes.POINTER(ctypes.c_int64)]
+    lib.lfsr_pool_submit.restype = I
+    lib.lfsr_pool_tick.argtypes = [PL, V, ctypes.POINTER(I)]
+    lib.lfsr_pool_tick.restype = I
+    lib.lfsr_pool_poll.argtypes = [PL, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(I), ctypes.POINTER(I), I,
+                                   ctypes.POINTER(I)]
+    lib.lfsr_pool_poll.restype = I
+    lib.lfsr_pool_info.argtypes = [PL, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_size_t)]
+    lib.lfsr_pool_info.restype = I
     _lib = lib
     return lib
 
@@ -112,10 +131,16 @@ def last_error(handle=None) -> str:
     return load().lfsr_last_error(handle).decode()
 
 
+STORAGE = {"f32": LFSR_F32, "f16": LFSR_F16, "bf16": LFSR_BF16}
+
+
 def make_params(cfg: dict, **over) -> lfsr_params:
-    """lfsr_params from a workload dict (keys as in synth.CONFIGS)."""
+    """lfsr_params from a workload dict (keys as in synth.CONFIGS); `storage`
+    may be an lfsr_storage value or one of "f32", "f16", "bf16"."""
     c = dict(cfg)
     c.update(over)
+    if isinstance(c.get("storage"), str):
+        c["storage"] = STORAGE[c["storage"]]
     return lfsr_params(
         ang_rows=c["U"], ang_cols=c["V"], lr_h=c["sy"], lr_w=c["sx"], scale=c["zeta"],
         n_disp=c.get("n_disp", 1), blur_size=c["kb"], blur_sigma=c["sigma_b"],
@@ -279,3 +304,73 @@ def disp_bound_for(disp, margin=1.0) -> float:
     import numpy as np
     m = float(np.max(np.abs(np.asarray(disp)))) if np.asarray(disp).size else 0.0
     return max(m * margin, 1e-3) if math.isfinite(m) else float("nan")
+
+
+class Pool:
+    """lfsr_pool over a torch-allocated device arena.  Each submitted job's
+    tensors are kept alive until the job is harvested by lfsr_pool_poll."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 16, device="cuda"):
+        self.lib = load()
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.lfsr_pool_create(ctypes.c_void_p(self.arena.data_ptr()), int(arena_bytes),
+                                              int(max_slots), ctypes.byref(h)), None)
+        self.handle = h
+        self.max_slots = int(max_slots)
+        self.jobs = {}
+
+    def _check(self, code, h):
+        if code != LFSR_OK:
+            raise LfsrError(code, self.lib.lfsr_pool_last_error(h).decode())
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            self.lib.lfsr_pool_destroy(self.handle)
+            self.handle = None
+            self.jobs.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def lfsr_pool_submit(self, params: lfsr_params, y, disp, occ=None, x0=None, out=None, stream=None):
+        """Job id, or None when the pool is full right now (LFSR_EBUSY)."""
+        H, W = params.scale * params.lr_h, params.scale * params.lr_w
+        out = torch.empty((H, W), dtype=torch.float32, device=self.device) if out is None else out
+        jid = ctypes.c_int64()
+        code = self.lib.lfsr_pool_submit(self.handle, ctypes.byref(params), _ptr(y), _ptr(disp), _ptr(occ),
+                                         _ptr(x0), _ptr(out), _stream(stream), ctypes.byref(jid))
+        if code == LFSR_EBUSY:
+            return None
+        self._check(code, self.handle)
+        self.jobs[jid.value] = (params, y, disp, occ, x0, out)
+        return jid.value
+
+    def lfsr_pool_tick(self, stream=None) -> int:
+        n = ctypes.c_int32()
+        self._check(self.lib.lfsr_pool_tick(self.handle, _stream(stream), ctypes.byref(n)), self.handle)
+        return n.value
+
+    def lfsr_pool_poll(self, cap: int = 64):
+        """[(job id, output tensor, status, iterations run)] of harvested jobs."""
+        ids = (ctypes.c_int64 * cap)()
+        st = (ctypes.c_int32 * cap)()
+        it = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        self._check(self.lib.lfsr_pool_poll(self.handle, ids, st, it, cap, ctypes.byref(n)), self.handle)
+        res = []
+        for i in range(n.value):
+            job = self.jobs.pop(ids[i])
+            res.append((ids[i], job[5], st[i], it[i]))
+        return res
+
+    def lfsr_pool_info(self):
+        a, r = ctypes.c_int32(), ctypes.c_int32()
+        f, big = ctypes.c_size_t(), ctypes.c_size_t()
+        self._check(self.lib.lfsr_pool_info(self.handle, ctypes.byref(a), ctypes.byref(r), ctypes.byref(f),
+                                            ctypes.byref(big)), self.handle)
+        return {"active": a.value, "retiring": r.value, "free": f.value, "largest_free": big.value}

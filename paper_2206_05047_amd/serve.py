@@ -1,0 +1,159 @@
+"""Request loop over the serving pool (lfsr_pool_*) and its one-job-at-a-time
+baseline, for a seeded Poisson stream of super-resolution jobs.
+
+Job types: angular 3x3 (N = 20), 5x5 (N = 50), 9x9 (N = 100) x (scale, HR
+size) in {(2, 256^2), (2, 512^2), (3, 768^2), (3, 1152^2)} x storage
+{f32, f16}, drawn uniformly; exponential inter-arrival times.  Each job's LR
+views are its type's LR views (one seeded scene per HR size, LR made with the
+library's forward model) plus seeded Gaussian noise of its own, so every job
+has distinct inputs.  Latency = result on the host minus arrival time.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+import torch
+
+from . import lfsr, synth
+
+ANGULAR = [(3, 20), (5, 50), (9, 100)]
+SPATIAL = [(2, 256), (2, 512), (3, 768), (3, 1152)]
+STORAGE = ["f32", "f16"]
+BLUR = {2: (7, 1.2), 3: (9, 1.5)}
+
+
+def job_types():
+    return [(a, n, z, hr, st) for (a, n) in ANGULAR for (z, hr) in SPATIAL for st in STORAGE]
+
+
+def _cfg(a, n, z, hr):
+    kb, sb = BLUR[z]
+    return synth.config("c3", U=a, V=a, sy=hr // z, sx=hr // z, zeta=z, kb=kb, sigma_b=sb, win=7, n_iter=n)
+
+
+class Workload:
+    """Per-type parameters and LR views on the device."""
+
+    def __init__(self, device="cuda", seed=5):
+        self.device = device
+        self.types = job_types()
+        self.scenes = {}
+        for z, hr in SPATIAL:
+            sc = synth.make_scene(synth.config("c3", sy=hr // z, sx=hr // z, zeta=z), seed=seed * 1000 + hr)
+            self.scenes[hr] = (torch.from_numpy(sc["x_gt"].astype(np.float32)).to(device),
+                               torch.from_numpy(sc["disp"].astype(np.float32)).to(device),
+                               float(np.abs(sc["disp"]).max()))
+        self.params, self.lr = [], []
+        for a, n, z, hr, st in self.types:
+            x, d, b = self.scenes[hr]
+            prm = lfsr.make_params(_cfg(a, n, z, hr), disp_bound=max(b, 1e-3), storage=st)
+            s = lfsr.Solver(lfsr.make_params(_cfg(a, n, z, hr), disp_bound=max(b, 1e-3)))
+            y = s.lfsr_forward(x, d)
+            s.close()
+            self.params.append(prm)
+            self.lr.append(y)
+        torch.cuda.synchronize()
+
+    def job_inputs(self, kind, job_id):
+        """LR views of one job: its type's views + N(0, 0.01^2), clipped to [0, 1]."""
+        g = torch.Generator(device=self.device).manual_seed(5_000_000 + job_id)
+        y = self.lr[kind]
+        y = (y + 0.01 * torch.randn(y.shape, device=self.device, generator=g)).clamp_(0.0, 1.0)
+        hr = self.types[kind][3]
+        return y, self.scenes[hr][1]
+
+    def work(self, kind):
+        """HR Mpixel-views x ADMM iterations of one job."""
+        a, n, z, hr, st = self.types[kind]
+        return hr * hr * a * a * n / 1e6
+
+
+def stream(n_jobs, rate, seed=5, n_types=24):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+    kinds = rng.integers(0, n_types, n_jobs)
+    return t - t[0], kinds
+
+
+def _summary(lat, work, t_end):
+    lat = np.asarray(lat)
+    return {"jobs": int(lat.size), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "mean_ms": float(lat.mean() * 1e3),
+            "makespan_s": float(t_end), "jobs_per_s": float(lat.size / t_end),
+            "mpv_iters_per_s": float(work / t_end)}
+
+
+def run_pool(wl: Workload, times, kinds, arena_bytes, max_slots=32, max_inflight=2):
+    """Serve the stream through one pool; returns the latency summary."""
+    pool = lfsr.Pool(arena_bytes, max_slots=max_slots)
+    copy_stream = torch.cuda.Stream()
+    pending = collections.deque()
+    arrival, lat, work = {}, [], 0.0
+    nxt, n = 0, len(times)
+    inflight = collections.deque()
+    head = None  # inputs of the job at the head of the queue
+    t0 = time.perf_counter()
+    while len(lat) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and times[nxt] <= now:
+            pending.append(nxt)
+            nxt += 1
+        while pending:
+            j = pending[0]
+            if head is None:
+                head = wl.job_inputs(int(kinds[j]), j)
+            jid = pool.lfsr_pool_submit(wl.params[int(kinds[j])], *head)
+            if jid is None:
+                break
+            pending.popleft()
+            head = None
+            arrival[jid] = (times[j], int(kinds[j]))
+        active = pool.lfsr_pool_tick()
+        if active:
+            ev = torch.cuda.Event()
+            ev.record()
+            inflight.append(ev)
+            if len(inflight) > max_inflight:
+                inflight.popleft().synchronize()
+        for jid, out, st, it in pool.lfsr_pool_poll():
+            with torch.cuda.stream(copy_stream):
+                host = out.to("cpu")
+            del host
+            t_arr, kind = arrival.pop(jid)
+            lat.append(time.perf_counter() - t0 - t_arr)
+            work += wl.work(kind)
+        if not active and not pending and nxt < n:
+            wait = times[nxt] - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.002))
+        elif not active and pool.lfsr_pool_info()["retiring"]:
+            torch.cuda.synchronize()
+    t_end = time.perf_counter() - t0
+    pool.close()
+    return _summary(lat, work, t_end)
+
+
+def run_fifo(wl: Workload, times, kinds):
+    """The plain method as a server: one lfsr_solve at a time, in arrival order."""
+    solvers = {}
+    lat, work = [], 0.0
+    t0 = time.perf_counter()
+    for j in range(len(times)):
+        now = time.perf_counter() - t0
+        if times[j] > now:
+            time.sleep(times[j] - now)
+        kind = int(kinds[j])
+        if kind not in solvers:
+            solvers[kind] = lfsr.Solver(wl.params[kind])
+        y, d = wl.job_inputs(kind, j)
+        out, _ = solvers[kind].lfsr_solve(y, d, stats=False)
+        host = out.to("cpu")  # synchronises
+        del host
+        lat.append(time.perf_counter() - t0 - times[j])
+        work += wl.work(kind)
+    t_end = time.perf_counter() - t0
+    for s in solvers.values():
+        s.close()
+    return _summary(lat, work, t_end)

@@ -53,6 +53,22 @@ def test_workspace_covers_the_state(lfsr, name):
     assert state <= n <= state * 1.5 + (1 << 20)
 
 
+@pytest.mark.parametrize("name", ["c1", "c2", "c3"])
+def test_16bit_storage_halves_the_stored_fields(lfsr, name):
+    """With F16/BF16 storage x, w_D, w_S and the LR stack take 2 bytes per
+    element; an FP32 remainder of x is added (the CG accumulator)."""
+    c = synth.config(name)
+    H, W = c["zeta"] * c["sy"], c["zeta"] * c["sx"]
+    sk, sd, q = c["U"] * c["V"], c["win"] ** 2 - 1, c["sy"] * c["sx"]
+    n32 = lfsr.workspace_bytes(_params(lfsr, name))
+    saved = 2 * (H * W + 2 * sk * q + 2 * sd * H * W) - 4 * H * W
+    for st in (lfsr.LFSR_F16, lfsr.LFSR_BF16):
+        p = _params(lfsr, name)
+        p.storage = st
+        n16 = lfsr.workspace_bytes(p)
+        assert abs((n32 - n16) - saved) <= 256 * 8
+
+
 @pytest.mark.parametrize("field,value", [
     ("ang_rows", 2), ("ang_cols", 0), ("lr_h", 0), ("scale", 0), ("scale", 9), ("n_disp", 9),
     ("blur_size", 4), ("blur_size", 33), ("lambda1", -1.0), ("nltv_window", 4), ("nltv_window", 17),
@@ -120,3 +136,24 @@ def test_iterate_before_init_is_a_state_error(lfsr):
     assert lib.lfsr_iterate(h, 1, None) == lfsr.LFSR_ESTATE
     assert lib.lfsr_init(h, None, None, None, None, None) == lfsr.LFSR_EINVAL
     lib.lfsr_destroy(h)
+
+
+def test_pool_argument_errors(lfsr):
+    """Pool creation checks its arguments before touching the device."""
+    lib = lfsr.load()
+    h = ctypes.c_void_p()
+    assert lib.lfsr_pool_create(None, 1 << 20, 4, ctypes.byref(h)) == lfsr.LFSR_ENOMEM and not h.value
+    assert lib.lfsr_pool_create(ctypes.c_void_p(1 << 20), 0, 4, ctypes.byref(h)) == lfsr.LFSR_ENOMEM
+    assert lib.lfsr_pool_create(ctypes.c_void_p((1 << 20) + 8), 1 << 20, 4, ctypes.byref(h)) == lfsr.LFSR_EINVAL
+    for slots in (0, 65):
+        assert lib.lfsr_pool_create(ctypes.c_void_p(1 << 20), 1 << 20, slots, ctypes.byref(h)) == lfsr.LFSR_EINVAL
+    assert lib.lfsr_pool_last_error(None).decode() != "no error"
+    n = ctypes.c_int32()
+    assert lib.lfsr_pool_tick(None, None, ctypes.byref(n)) == lfsr.LFSR_EINVAL
+    assert lib.lfsr_pool_poll(None, None, None, None, 0, ctypes.byref(n)) == lfsr.LFSR_EINVAL
+    assert lib.lfsr_pool_info(None, None, None, None, None) == lfsr.LFSR_EINVAL
+    jid = ctypes.c_int64()
+    p = _params(lfsr)
+    assert lib.lfsr_pool_submit(None, ctypes.byref(p), None, None, None, None, None, None,
+                                ctypes.byref(jid)) == lfsr.LFSR_EINVAL
+    lib.lfsr_pool_destroy(None)
