@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=8, help="ADMM iterations of the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=0, help="override the ADMM iteration count (profiling only)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP16/BF16 storage runs")
+    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs in the serving stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="serving arrival rate, jobs/s")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
@@ -181,6 +184,50 @@ def main():
         "roofline": roof,
         "kernel_ms_per_solve": {k: v[0] for k, v in breakdown.items()},
     }
+
+    if not args.no_precision:
+        # the same workload with the state stored in 16 bits (FP32 stencil arithmetic)
+        ref = out.cpu().numpy().astype(np.float64)
+        prec = {}
+        for st in ("f16", "bf16"):
+            s16 = lfsr.Solver(lfsr.make_params(cfg, disp_bound=max(bound, 1e-3), storage=st))
+            o16 = torch.empty_like(out)
+            s16.lfsr_solve(y, disp, out=o16, stats=False)
+            torch.cuda.synchronize()
+            n16 = max(1, min(args.steps, 3))
+            ta = time.perf_counter()
+            for _ in range(n16):
+                s16.lfsr_solve(y, disp, out=o16, stats=False)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            x16 = o16.cpu().numpy().astype(np.float64)
+            prec[st] = {
+                "value": H * W * sk * N * n16 / (tb - ta) / 1e6,
+                "ms_per_step": (tb - ta) * 1e3 / n16,
+                "speedup_vs_f32": ms / ((tb - ta) * 1e3 / n16),
+                "rel_l2_vs_f32": synth.rel_l2(x16, ref),
+                "psnr_gt": synth.psnr(x16, sc["x_gt"]),
+                "psnr_f32": synth.psnr(ref, sc["x_gt"]),
+                "workspace_bytes": s16.bytes,
+                "steps": n16,
+            }
+            s16.close()
+            log(f"[bench] {st}: {prec[st]['ms_per_step']:.2f} ms/solve, rel_l2 vs f32 {prec[st]['rel_l2_vs_f32']:.2e}")
+        line["precision"] = prec
+
+    if args.serve_jobs > 0:
+        from paper_2206_05047_amd import serve
+
+        wl = serve.Workload()
+        times, kinds = serve.stream(args.serve_jobs, args.serve_rate)
+        pool = serve.run_pool(wl, times, kinds, arena_bytes=40 << 30, max_slots=32)
+        log(f"[bench] serving pool: {pool}")
+        fifo = serve.run_fifo(wl, times, kinds)
+        log(f"[bench] serving one-at-a-time: {fifo}")
+        line["serving"] = {"workload": f"{args.serve_jobs} seeded jobs, Poisson arrivals at {args.serve_rate:g} jobs/s, "
+                                       "types uniform over 3x3/5x5/9x9 views x (x2 256^2, x2 512^2, x3 768^2, "
+                                       "x3 1152^2) x f32/f16 storage",
+                           "pool": pool, "one_at_a_time": fifo}
 
     if not args.no_cpu_baseline:
         import oracle

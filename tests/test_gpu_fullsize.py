@@ -134,3 +134,21 @@ def test_c3_one_iteration_matches_oracle(lfsr):
     assert rel_err(_n(st["wD"]), ref["wD"]) < 2e-5
     assert rel_err(_n(st["wS"]), ref["wS"]) < 2e-5
     assert synth.rel_l2(_n(st["x"]), ref["x"]) < 1e-5
+
+
+@pytest.mark.parametrize("st,tol", [("f16", 2e-3), ("bf16", 1.5e-2)])
+def test_c3_16bit_storage_against_stored_oracle(lfsr, st, tol):
+    """The precision form of the large workload: relative L2 on the samples
+    and PSNR against the ground truth, both against the FP64 oracle (bounds
+    as for the small cases, see test_gpu_precision)."""
+    c = _case("c3")
+    g = _golden("c3", c)
+    bound = float(np.abs(c["sc"]["disp"]).max())
+    s = lfsr.Solver(lfsr.make_params(c["cfg"], disp_bound=bound, storage=st))
+    x, _ = s.lfsr_solve(_t(c["y"]), _t(c["sc"]["disp"]))
+    x = _n(x)
+    err = synth.rel_l2(x.ravel()[g["idx"]], g["x_samples"])
+    p16 = synth.psnr(x, c["sc"]["x_gt"])
+    print(f"c3 {st}: rel_l2(samples)={err:.3e} psnr={p16:.3f} (oracle {float(g['psnr_gt']):.3f})", flush=True)
+    assert err < tol
+    assert abs(p16 - float(g["psnr_gt"])) <= 0.05
