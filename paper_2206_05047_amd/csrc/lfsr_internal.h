@@ -46,8 +46,10 @@ struct Geom {
   float cg_tol;
   float stop_tol;
   int n_iter;                 // rows of the statistics history
-  // forward-operator tiling: LR tile and views per block
+  // forward-operator tiling: LR tile and views per block.  f_col = 1 selects
+  // the column-per-lane kernel (then f_vpb = 4 waves x views per wave).
   int f_tly, f_tlx, f_vpb;
+  int f_col;
   // adjoint tiling: LR tile, HR tile, extended (haloed) tile, tile grid
   int a_tly, a_tlx, a_th, a_tw, a_ey, a_ex, a_nty, a_ntx;
   float a_inv_th, a_inv_tw;   // 1/a_th, 1/a_tw (division-free tile lookup)
@@ -109,6 +111,9 @@ size_t forward_lds(const Geom& g);
 size_t adjoint_lds(const Geom& g);
 size_t tv_lds(const Geom& g);
 bool forward_tile_ok(const Geom& g);
+// switch g to the column-per-lane forward kernel when its shape is compiled
+// and its tile fits (sets f_col, f_tly, f_tlx; the caller sets f_vpb)
+bool forward_col_setup(Geom& g);
 bool adjoint_tile_ok(const Geom& g);
 dim3 forward_grid(const Geom& g);
 dim3 adjoint_grid(const Geom& g);

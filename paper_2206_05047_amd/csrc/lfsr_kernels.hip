@@ -316,6 +316,158 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Forward operator, column-per-lane form (same result as k_forward, same
+// fused wz-step epilogue).  A block stages the HR source tile of one LR tile
+// (TLY x f_tlx lattice points) once; each of its four waves then takes whole
+// views (k0 + wave, k0 + wave + 4, ...), so the view loop has no block
+// barrier.  Lane px owns column px of the blur positions (NX <= 64): it walks
+// the NY positions of its column, warps each one by a bilinear gather from
+// the staged tile and feeds it straight into the vertical blur at the lattice
+// rows, held in registers; the wave then applies the horizontal blur at the
+// lattice columns from a wave-private LDS row buffer.  ZETA, KB and TLY are
+// compile-time so that the position walk and the tap selection unroll.
+// grid = (ceil(sx/f_tlx), ceil(sy/TLY), ceil(sk/f_vpb)).
+template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO>
+__global__ __launch_bounds__(kThreads) void k_fwdcol(Geom g, const TS* __restrict__ src,
+                                                     const float* __restrict__ disp, TO* __restrict__ out,
+                                                     const float* __restrict__ y, TO* __restrict__ wD,
+                                                     double* __restrict__ part, float* __restrict__ pmax,
+                                                     const DevScalars* __restrict__ sc, int gate) {
+  if (gated(sc, g, gate)) return;
+  constexpr int RB = KB / 2;
+  constexpr int NY = (TLY - 1) * ZETA + KB;
+  constexpr int NO = (TLY * ((64 - KB) / ZETA + 1) + 63) / 64;  // outputs per lane and view
+  extern __shared__ float smem[];
+  const int h = g.halo, tlx = g.f_tlx;
+  const int NX = (tlx - 1) * ZETA + KB;
+  const int SY = NY + 2 * h, SX = NX + 2 * h;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* xs = smem;                                  // [SY][SX] source tile, zero outside the image
+  float* vb = smem + SY * SX + wave * (TLY * NX);    // wave-private [TLY][NX] vertical-blur rows
+  const int i0 = blockIdx.y * TLY, j0 = blockIdx.x * tlx;
+  const int Yp0 = i0 * ZETA - RB, Xp0 = j0 * ZETA - RB;
+  stage_tile(xs, SX, src, g.H, g.W, Yp0 - h, Xp0 - h, SY, SX);
+
+  // this lane's column of blur positions: clamped disparity, 0 outside the
+  // image (the zero tile then makes the sample vanish, as B's zero padding
+  // requires); lanes beyond NX address column 0 and discard their results
+  const bool colok = lane < NX;
+  const int px = colok ? lane : 0;
+  const int X = Xp0 + px;
+  float om[NY];
+#pragma unroll
+  for (int py = 0; py < NY; ++py) {
+    const int Y = Yp0 + py;
+    const bool in = colok && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
+    om[py] = disp[in ? (size_t)Y * g.W + X : 0];
+    om[py] = in ? fminf(fmaxf(om[py], -g.disp_bound), g.disp_bound) : 0.f;
+  }
+  const int cbase = h * SX + px + h;  // tile offset of (row 0, this column)
+  // outputs of this lane: lattice point (oi, oj) of the tile, slot s
+  const float invT = 1.f / (float)tlx;
+  int orow[NO], ocol[NO];
+  bool oval[NO];
+  size_t oofs[NO];
+#pragma unroll
+  for (int s = 0; s < NO; ++s) {
+    const int idx = lane + 64 * s;
+    const int a = (int)(((float)idx + 0.5f) * invT), b = idx - a * tlx;
+    orow[s] = a;
+    ocol[s] = b;
+    oval[s] = idx < TLY * tlx && i0 + a < g.sy && j0 + b < g.sx;
+    oofs[s] = oval[s] ? (size_t)(i0 + a) * g.sx + (j0 + b) : 0;
+  }
+  __syncthreads();
+
+  double s_abs = 0.0, s_sq = 0.0, s_dw = 0.0;
+  float vmax = 0.f;
+  const int k0 = blockIdx.z * g.f_vpb;
+  const int k1 = min(g.sk, k0 + g.f_vpb);
+  for (int k = k0 + wave; k < k1; k += 4) {
+    const int ka = k / g.V, kc = k - ka * g.V;
+    const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
+    const size_t vo = (size_t)k * g.q;
+    float yv[NO], w0[NO];
+    if constexpr (WZD) {  // issued early; consumed after the position walk
+#pragma unroll
+      for (int s = 0; s < NO; ++s) {
+        yv[s] = y[vo + oofs[s]];
+        w0[s] = (float)wD[vo + oofs[s]];
+      }
+    }
+    float acc[TLY];
+#pragma unroll
+    for (int i = 0; i < TLY; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int py = 0; py < NY; ++py) {
+      const float sy = tau * om[py], sx = rho * om[py];
+      const float fy0 = floorf(sy), fx0 = floorf(sx);
+      const float fy = sy - fy0, fx = sx - fx0;
+      // |row| < 2^23: the 24-bit multiply is exact
+      const int off = cbase + __mul24(py + (int)fy0, SX) + (int)fx0;
+      const float a = xs[off], b = xs[off + 1], c = xs[off + SX], d = xs[off + SX + 1];
+      const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
+      const float val = fmaf(fy, bot - top, top);
+#pragma unroll
+      for (int i = 0; i < TLY; ++i) {
+        const int t = py - i * ZETA;  // tap of lattice row i (compile-time after unrolling)
+        if (t >= 0 && t < KB) acc[i] = fmaf(g.g[t], val, acc[i]);
+      }
+    }
+    if (colok) {
+#pragma unroll
+      for (int i = 0; i < TLY; ++i) vb[i * NX + px] = acc[i];
+    }
+    __builtin_amdgcn_wave_barrier();  // the wave's LDS writes precede its reads below
+#pragma unroll
+    for (int s = 0; s < NO; ++s) {
+      if (!oval[s]) continue;
+      const float* rowp = vb + orow[s] * NX + ocol[s] * ZETA;
+      float t = 0.f;
+#pragma unroll
+      for (int b = 0; b < KB; ++b) t = fmaf(g.g[b], rowp[b], t);
+      const size_t o = vo + oofs[s];
+      if constexpr (!WZD) {
+        const TO ts = (TO)t;
+        out[o] = ts;
+        vmax = fmaxf(vmax, fabsf((float)ts));
+      } else {
+        const float r = t - yv[s];
+        const float wn = clipf(fmaf(g.lambda1, r, w0[s]), g.clip);
+        const float e = g.lambda2 * r + g.half_theta * g.lambda1 * (2.f * wn - w0[s]);
+        const TO es = (TO)e;
+        out[o] = es;
+        vmax = fmaxf(vmax, fabsf((float)es));
+        wD[o] = (TO)wn;
+        const double rd = (double)r, dw = (double)wn - (double)w0[s];
+        s_abs += fabs(rd);
+        s_sq += rd * rd;
+        s_dw += dw * dw;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();  // reads of vb complete before the next view overwrites it
+  }
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
+    __shared__ float sm[4];
+    if (lane == 0) sm[wave] = vmax;
+    __syncthreads();
+    if (tid == 0) pmax[bid] = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+  }
+  if constexpr (WZD) {
+    double v[3] = {s_abs, s_sq, s_dw};
+    block_sum<3>(v);
+    if (tid == 0) {
+      part[(size_t)bid * 3 + 0] = v[0];
+      part[(size_t)bid * 3 + 1] = v[1];
+      part[(size_t)bid * 3 + 2] = v[2];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint sum_k A_k^T lr_k = sum_k W_k^T B^T D^T lr_k into per-tile partial
 // images [tile][a_ey][a_ex] (HR tile + warp halo).  grid = (a_ntx, a_nty).
 //
@@ -1077,7 +1229,30 @@ static inline void fwd_dims(const Geom& g, int& NY, int& NX, int& SY, int& SX) {
 size_t forward_lds(const Geom& g) {
   int NY, NX, SY, SX;
   fwd_dims(g, NY, NX, SY, SX);
+  if (g.f_col) return sizeof(float) * ((size_t)SY * SX + 4 * (size_t)g.f_tly * NX);
   return sizeof(float) * ((size_t)SY * SX + (size_t)NY * NX + (size_t)NY * g.f_tlx);
+}
+
+// (zeta, blur size) pairs with a compiled column-per-lane forward kernel, and
+// its lattice rows per tile
+static constexpr bool fwdcol_shape(int zeta, int kb) {
+  return (zeta == 2 && (kb == 3 || kb == 5 || kb == 7 || kb == 9)) || (zeta == 3 && (kb == 5 || kb == 7 || kb == 9)) ||
+         (zeta == 4 && (kb == 7 || kb == 9));
+}
+static constexpr int fwdcol_tly(int zeta, int kb) { return 15 * zeta + kb <= 64 ? 16 : 8; }
+
+bool forward_col_setup(Geom& g) {
+  if (!fwdcol_shape(g.zeta, g.kb)) return false;
+  Geom t = g;
+  t.f_col = 1;
+  t.f_tly = fwdcol_tly(g.zeta, g.kb);
+  const int tmax = (64 - g.kb) / g.zeta + 1;  // NX <= 64
+  // the widest tile with the fewest tile columns
+  const int ncol = (g.sx + tmax - 1) / tmax;
+  t.f_tlx = (g.sx + ncol - 1) / ncol;
+  if (forward_lds(t) > 60 * 1024) return false;
+  g = t;
+  return true;
 }
 
 bool forward_tile_ok(const Geom& g) {
@@ -1140,6 +1315,19 @@ static void launch_fwd_kb(const Geom& g, const TS* src, const float* disp, TO* o
                           double* part, float* pmax, const DevScalars* sc, int gate, hipStream_t s) {
   const dim3 grid = forward_grid(g), blk(kThreads);
   const size_t lds = forward_lds(g);
+  if (g.f_col) {
+#define LFSR_FWC(Z, K)                                                                                             \
+  if (g.zeta == Z && g.kb == K) {                                                                                  \
+    constexpr int TL = fwdcol_tly(Z, K);                                                                           \
+    hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO>), grid, blk, lds, s, g, src, disp, out, y, wD, part, pmax, \
+                       sc, gate);                                                                                  \
+    return;                                                                                                        \
+  }
+    LFSR_FWC(2, 3) LFSR_FWC(2, 5) LFSR_FWC(2, 7) LFSR_FWC(2, 9) LFSR_FWC(3, 5) LFSR_FWC(3, 7) LFSR_FWC(3, 9)
+    LFSR_FWC(4, 7) LFSR_FWC(4, 9)
+#undef LFSR_FWC
+    return;  // unreachable: forward_col_setup admits only the shapes above
+  }
 #define LFSR_FWD(KB) \
   hipLaunchKernelGGL((k_forward<WZD, KB, TS, TO>), grid, blk, lds, s, g, src, disp, out, y, wD, part, pmax, sc, gate)
   switch (g.kb) {
