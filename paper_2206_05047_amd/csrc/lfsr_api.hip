@@ -88,6 +88,10 @@ bool choose_tiles(Geom& g, std::string* err) {
   g.a_ntx = (g.sx + g.a_tlx - 1) / g.a_tlx;
   g.a_inv_th = (float)(1.0 / g.a_th);
   g.a_inv_tw = (float)(1.0 / g.a_tw);
+  g.a_col = 0;
+  g.a_vg = 1;
+  g.a_vpb = g.sk;
+  (void)adjoint_col_setup(g);
   long long rbk = (g.p + 4 * kThreads - 1) / (4 * kThreads);
   g.red_blocks = (int)(rbk < kRedBlocks ? (rbk < 1 ? 1 : rbk) : kRedBlocks);
   return true;
@@ -213,7 +217,7 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   pl->off_ws0 = take((size_t)g.sd * P * es);
   pl->off_ws1 = take((size_t)g.sd * P * es);
   pl->off_lr = take((size_t)g.sk * Q * es);
-  pl->off_adj = take((size_t)g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4);
+  pl->off_adj = take((size_t)g.a_vg * g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4);
   {
     const dim3 fg = forward_grid(g), tg = tv_grid(g);
     pl->off_pwzd = take((size_t)fg.x * fg.y * fg.z * 3 * sizeof(double));

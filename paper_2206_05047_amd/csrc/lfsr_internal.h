@@ -52,6 +52,9 @@ struct Geom {
   int f_col;
   // adjoint tiling: LR tile, HR tile, extended (haloed) tile, tile grid
   int a_tly, a_tlx, a_th, a_tw, a_ey, a_ex, a_nty, a_ntx;
+  // a_col = 1: column-per-lane adjoint; views split into a_vg groups of a_vpb,
+  // each group writing its own set of partial images
+  int a_col, a_vg, a_vpb;
   float a_inv_th, a_inv_tw;   // 1/a_th, 1/a_tw (division-free tile lookup)
   int red_blocks;             // grid of the element-wise CG kernels
 };
@@ -115,6 +118,9 @@ bool forward_tile_ok(const Geom& g);
 // and its tile fits (sets f_col, f_tly, f_tlx; the caller sets f_vpb)
 bool forward_col_setup(Geom& g);
 bool adjoint_tile_ok(const Geom& g);
+// switch g to the column-per-lane adjoint when its shape is compiled and its
+// tile fits (sets a_col, the tile fields and the view groups)
+bool adjoint_col_setup(Geom& g);
 dim3 forward_grid(const Geom& g);
 dim3 adjoint_grid(const Geom& g);
 dim3 tv_grid(const Geom& g);

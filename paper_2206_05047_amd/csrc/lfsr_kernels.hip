@@ -121,18 +121,21 @@ __device__ __forceinline__ float adj_merge(const Geom& g, const float* __restric
   const int ty = (int)(((float)Y + 0.5f) * g.a_inv_th), tx = (int)(((float)X + 0.5f) * g.a_inv_tw);
   const int ly = Y - ty * g.a_th, lx = X - tx * g.a_tw;
   const size_t tile = (size_t)g.a_ey * g.a_ex;
+  const size_t grp = (size_t)g.a_nty * g.a_ntx * tile;
   float s = 0.f;
+  for (int z = 0; z < g.a_vg; ++z) {
 #pragma unroll
-  for (int a = -1; a <= 1; ++a) {
-    const int tty = ty + a;
-    const int ey = ly - a * g.a_th + g.halo;
-    if (tty < 0 || tty >= g.a_nty || ey < 0 || ey >= g.a_ey) continue;
+    for (int a = -1; a <= 1; ++a) {
+      const int tty = ty + a;
+      const int ey = ly - a * g.a_th + g.halo;
+      if (tty < 0 || tty >= g.a_nty || ey < 0 || ey >= g.a_ey) continue;
 #pragma unroll
-    for (int b = -1; b <= 1; ++b) {
-      const int ttx = tx + b;
-      const int ex = lx - b * g.a_tw + g.halo;
-      if (ttx < 0 || ttx >= g.a_ntx || ex < 0 || ex >= g.a_ex) continue;
-      s += adj[((size_t)tty * g.a_ntx + ttx) * tile + (size_t)ey * g.a_ex + ex];
+      for (int b = -1; b <= 1; ++b) {
+        const int ttx = tx + b;
+        const int ex = lx - b * g.a_tw + g.halo;
+        if (ttx < 0 || ttx >= g.a_ntx || ex < 0 || ex >= g.a_ex) continue;
+        s += adj[z * grp + ((size_t)tty * g.a_ntx + ttx) * tile + (size_t)ey * g.a_ex + ex];
+      }
     }
   }
   return s;
@@ -690,6 +693,175 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
   __syncthreads();
   float* o = outp + ((size_t)ty * g.a_ntx + tx) * (size_t)(EY * EX);
   for (int idx = tid; idx < EY * EX; idx += kThreads) o[idx] = (float)acc[idx] * invS;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint, column-per-lane form (same operator as k_adjoint).  A block owns an
+// HR tile of adjcol_th(ZETA) rows x adjcol_tw(ZETA) columns plus the warp
+// halo, in a shared 64-bit fixed-point accumulator (as in k_adjoint); its
+// four waves take views k0 + wave, k0 + wave + 4, ... of the block's view
+// group.  Lane x owns tile column x and walks the tile rows: B^T D^T is a
+// horizontal polyphase pass per staged LR row (three LDS reads) followed by a
+// vertical pass in registers with compile-time taps, so a pixel costs a
+// fraction of an LDS read instead of several; then W_k^T sends u to the four
+// cells W_k reads.  The per-pixel instruction count is what bounds this
+// kernel on gfx950 (a wave64 VALU instruction occupies a 16-lane SIMD for four
+// cycles), so the row step is kept to the bare arithmetic.
+static constexpr int adjcol_tw(int zeta) { return zeta * (63 / zeta); }
+static constexpr int adjcol_th(int zeta) { return zeta * (33 / zeta); }
+static constexpr int cdiv_c(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
+
+template <int ZETA, int KB, typename TI>
+__global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restrict__ lr,
+                                                     const float* __restrict__ disp, float* __restrict__ outp,
+                                                     const float* __restrict__ pmax, int npmax,
+                                                     const DevScalars* __restrict__ sc, int gate) {
+  if (gated(sc, g, gate)) return;
+  constexpr int RB = KB / 2;
+  constexpr int TW = adjcol_tw(ZETA), TH = adjcol_th(ZETA);
+  constexpr int CF = RB / ZETA;
+  constexpr int RL = (TH - 1 + RB) / ZETA + CF + 1;  // staged LR rows
+  constexpr int LX = (TW - 1 + RB) / ZETA + CF + 1;  // staged LR columns
+  constexpr int ESL = (RL * LX + 63) / 64;
+  constexpr int MM = (2 * RB) / ZETA + 1;            // taps per polyphase phase (at most)
+  extern __shared__ long long smem8[];
+  const int h = g.halo, EY = g.a_ey, EX = g.a_ex;  // EY = TH + 2h, EX = TW + 2h
+  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem8);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* e_ = reinterpret_cast<float*>(smem8 + EY * EX) + wave * (RL * LX);  // wave-private LR rows
+  for (int i = tid; i < EY * EX; i += kThreads) acc[i] = 0;
+
+  // fixed-point scale from the producer's block maxima (order-free, so exact)
+  float mloc = 0.f;
+  for (int i = tid; i < npmax; i += kThreads) mloc = fmaxf(mloc, pmax[i]);
+  __shared__ float smax[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, off, 64));
+  if (lane == 0) smax[wave] = mloc;
+  __syncthreads();
+  const float M = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
+  int eM = 0;
+  if (M > 0.f) (void)frexpf(M, &eM);  // M < 2^eM
+  const int sexp = min(max(30 - eM, -120), 120);
+  const float S = ldexpf(1.f, sexp), invS = ldexpf(1.f, -sexp);
+
+  const int Y0 = blockIdx.y * TH, X0 = blockIdx.x * TW;  // tile origin (multiples of ZETA)
+  const int i0 = Y0 / ZETA - CF, jb = X0 / ZETA - CF;    // first staged LR row / column
+  // staged LR values of this lane (offset within a view; -1 = zero)
+  int eoff[ESL];
+#pragma unroll
+  for (int s = 0; s < ESL; ++s) {
+    const int idx = lane + 64 * s;
+    const int a = idx / LX, b = idx - a * LX;
+    const int i = i0 + a, j = jb + b;
+    eoff[s] = (idx < RL * LX && i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? i * g.sx + j : -1;
+  }
+  // this lane's column: own pixel (x < TW) or idle
+  const bool own = lane < TW;
+  const int x = own ? lane : 0;
+  const int X = X0 + x;
+  const bool colin = own && X < g.W;
+  // horizontal taps of this column's phase, LR column indices within the staged rows
+  float gh[MM];
+  int jr[MM];
+  {
+    const int ph = x % ZETA, q = x / ZETA;
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+      gh[m] = 0.f;
+      jr[m] = 0;
+    }
+#pragma unroll
+    for (int p = 0; p < ZETA; ++p) {
+      if (ph != p) continue;
+#pragma unroll
+      for (int m = 0; m < MM; ++m) {
+        const int lo = cdiv_c(p - RB, ZETA);
+        const int t = ZETA * (lo + m) - p + RB;
+        gh[m] = t <= 2 * RB ? g.g[t] : 0.f;
+        jr[m] = min(q + lo + m + CF, LX - 1);
+      }
+    }
+  }
+  // disparity of the column (clamped; 0 outside the image)
+  float om[TH];
+#pragma unroll
+  for (int r = 0; r < TH; ++r) {
+    const int Y = Y0 + r;
+    const bool in = colin && Y < g.H;
+    om[r] = disp[in ? (size_t)Y * g.W + X : 0];
+    om[r] = in ? fminf(fmaxf(om[r], -g.disp_bound), g.disp_bound) : 0.f;
+  }
+  float ereg[ESL];
+  const int k0 = blockIdx.z * g.a_vpb;
+  const int k1 = min(g.sk, k0 + g.a_vpb);
+  int k = k0 + wave;
+  if (k < k1) {
+#pragma unroll
+    for (int s = 0; s < ESL; ++s) {
+      const float t = (float)lr[(size_t)k * g.q + (eoff[s] >= 0 ? eoff[s] : 0)];
+      ereg[s] = eoff[s] >= 0 ? t : 0.f;
+    }
+  }
+  __syncthreads();  // accumulator zeroed
+
+  for (; k < k1; k += 4) {
+#pragma unroll
+    for (int s = 0; s < ESL; ++s)
+      if (lane + 64 * s < RL * LX) e_[lane + 64 * s] = ereg[s];
+    if (k + 4 < k1) {  // prefetch this wave's next view
+#pragma unroll
+      for (int s = 0; s < ESL; ++s) {
+        const float t = (float)lr[(size_t)(k + 4) * g.q + (eoff[s] >= 0 ? eoff[s] : 0)];
+        ereg[s] = eoff[s] >= 0 ? t : 0.f;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // B^T D^T, horizontal: one value per staged LR row, scaled by S
+    float hrow[RL];
+#pragma unroll
+    for (int a = 0; a < RL; ++a) {
+      float t = 0.f;
+#pragma unroll
+      for (int m = 0; m < MM; ++m) t = fmaf(gh[m], e_[a * LX + jr[m]], t);
+      hrow[a] = t * S;
+    }
+    __builtin_amdgcn_wave_barrier();  // reads of e_ precede the next view's staging
+    if (!own) continue;  // the idle lanes of the wave (wave-uniform except for them)
+    const int ka = k / g.V, kc = k - ka * g.V;
+    const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
+#pragma unroll
+    for (int r = 0; r < TH; ++r) {
+      // B^T D^T, vertical (compile-time taps of row phase r % ZETA)
+      float u = 0.f;
+      {
+        const int pr = r % ZETA, qr = r / ZETA;
+        const int lo = cdiv_c(pr - RB, ZETA);
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+          const int t = ZETA * (lo + m) - pr + RB;
+          if (t <= 2 * RB) u = fmaf(g.g[t], hrow[qr + lo + m + CF], u);
+        }
+      }
+      u = (colin && Y0 + r < g.H) ? u : 0.f;
+      const float sy = tau * om[r], sx = rho * om[r];
+      const float fy0 = floorf(sy), fx0 = floorf(sx);
+      const float wy1 = sy - fy0, wx1 = sx - fx0;
+      const float u1 = u * wy1, u0 = u - u1;
+      const float br = u1 * wx1, bl = u1 - br, tr = u0 * wx1, tl = u0 - tr;
+      // W_k^T: the four cells W_k read (two row bases, +1 column as an immediate offset)
+      unsigned long long* c0 = acc + __mul24(r + h + (int)fy0, EX) + (x + h + (int)fx0);
+      unsigned long long* c1 = c0 + EX;
+      atomicAdd(c0, (unsigned long long)(long long)(int)tl);
+      atomicAdd(c0 + 1, (unsigned long long)(long long)(int)tr);
+      atomicAdd(c1, (unsigned long long)(long long)(int)bl);
+      atomicAdd(c1 + 1, (unsigned long long)(long long)(int)br);
+    }
+  }
+  __syncthreads();
+  const size_t tiles = (size_t)g.a_nty * g.a_ntx;
+  float* o = outp + ((size_t)blockIdx.z * tiles + (size_t)blockIdx.y * g.a_ntx + blockIdx.x) * (size_t)(EY * EX);
+  for (int idx = tid; idx < EY * EX; idx += kThreads) o[idx] = (float)(long long)acc[idx] * invS;
 }
 
 // Per-block max |v| of n floats (scale input of the adjoint entry point).
@@ -1271,6 +1443,11 @@ static inline void adj_dims(const Geom& g, int& ci, int& LY, int& LX, int& MM, i
 }
 
 size_t adjoint_lds(const Geom& g) {
+  if (g.a_col) {
+    const int z = g.zeta, CF = g.rb / z;
+    const int RL = (g.a_th - 1 + g.rb) / z + CF + 1, LXc = (g.a_tw - 1 + g.rb) / z + CF + 1;
+    return 8 * (size_t)g.a_ey * g.a_ex + sizeof(float) * 4 * (size_t)RL * LXc;
+  }
   int ci, LY, LX, MM, PAD;
   adj_dims(g, ci, LY, LX, MM, PAD);
   const int RH = g.a_th / 4, RL = RH / g.zeta + 2 * ci;
@@ -1294,7 +1471,49 @@ size_t tv_lds(const Geom& g) {
 dim3 forward_grid(const Geom& g) {
   return dim3((g.sx + g.f_tlx - 1) / g.f_tlx, (g.sy + g.f_tly - 1) / g.f_tly, (g.sk + g.f_vpb - 1) / g.f_vpb);
 }
-dim3 adjoint_grid(const Geom& g) { return dim3(g.a_ntx, g.a_nty, 1); }
+dim3 adjoint_grid(const Geom& g) { return dim3(g.a_ntx, g.a_nty, g.a_vg); }
+
+static constexpr bool adjcol_shape(int zeta, int kb) { return fwdcol_shape(zeta, kb); }
+
+bool adjoint_col_setup(Geom& g) {
+  if (!adjcol_shape(g.zeta, g.kb)) return false;
+  Geom t = g;
+  t.a_col = 1;
+  t.a_th = adjcol_th(g.zeta);
+  t.a_tw = adjcol_tw(g.zeta);
+  if (g.halo > t.a_th || g.halo > t.a_tw) return false;  // partial images may overlap only neighbouring tiles
+  t.a_tly = t.a_th / g.zeta;
+  t.a_tlx = t.a_tw / g.zeta;
+  t.a_ey = t.a_th + 2 * g.halo;
+  t.a_ex = t.a_tw + 2 * g.halo;
+  const size_t lds = adjoint_lds(t);
+  if (lds > 64 * 1024) return false;
+  t.a_nty = (g.H + t.a_th - 1) / t.a_th;
+  t.a_ntx = (g.W + t.a_tw - 1) / t.a_tw;
+  t.a_inv_th = (float)(1.0 / t.a_th);
+  t.a_inv_tw = (float)(1.0 / t.a_tw);
+  // view groups: a block's time grows with its views, a launch takes
+  // ceil(blocks / resident slots) rounds, and every extra group adds a set of
+  // partial images to merge; pick the group count with the lowest estimate
+  long long per_cu = (long long)((160 * 1024) / lds);
+  if (per_cu > 5) per_cu = 5;
+  if (per_cu < 1) per_cu = 1;
+  const long long slots = 256 * per_cu, tiles = (long long)t.a_nty * t.a_ntx;
+  int best_g = 1;
+  double best = 1e30;
+  for (int G = 1; G <= 8 && G <= g.sk; ++G) {
+    const double rounds = (double)((tiles * G + slots - 1) / slots);
+    const double cost = rounds / G + 0.02 * G;
+    if (cost < best - 1e-12) {
+      best = cost;
+      best_g = G;
+    }
+  }
+  t.a_vpb = (g.sk + best_g - 1) / best_g;
+  t.a_vg = (g.sk + t.a_vpb - 1) / t.a_vpb;
+  g = t;
+  return true;
+}
 dim3 tv_grid(const Geom& g) { return dim3((g.W + kTvTileX - 1) / kTvTileX, (g.H + kTvTileY - 1) / kTvTileY, 1); }
 
 static inline int nblocks(dim3 d) { return (int)(d.x * d.y * d.z); }
@@ -1372,6 +1591,17 @@ void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp,
   by_storage(lr_st, [&](auto* tag) {
     using T = LFSR_ELEM(tag);
     const T* in = (const T*)lr;
+    if (g.a_col) {
+#define LFSR_ADC(Z, K)                                                                                          \
+  if (g.zeta == Z && g.kb == K) {                                                                               \
+    hipLaunchKernelGGL((k_adjcol<Z, K, T>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, sc, gate);        \
+    return;                                                                                                     \
+  }
+      LFSR_ADC(2, 3) LFSR_ADC(2, 5) LFSR_ADC(2, 7) LFSR_ADC(2, 9) LFSR_ADC(3, 5) LFSR_ADC(3, 7) LFSR_ADC(3, 9)
+      LFSR_ADC(4, 7) LFSR_ADC(4, 9)
+#undef LFSR_ADC
+      return;  // unreachable: adjoint_col_setup admits only the shapes above
+    }
 #define LFSR_ADJ(M) hipLaunchKernelGGL((k_adjoint<M, T>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, sc, gate)
     switch (MM) {
       case 1: LFSR_ADJ(1); break;
