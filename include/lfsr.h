@@ -172,6 +172,7 @@ lfsr_status lfsr_get_stats(lfsr_handle* h, lfsr_stats* out, void* hip_stream);
  *                 (the x-step normal operator G^T G of sec 5); the
  *                 intermediate A d_p is stored in the handle's storage type,
  *                 exactly as in the solver's CG steps.
+ *                 d_out must not alias d_p or d_m (LFSR_EINVAL).
  * lfsr_forward / lfsr_adjoint are FP32 throughout whatever the storage type.
  * They use the handle's work buffers, so they must not overlap an iteration. */
 lfsr_status lfsr_forward(lfsr_handle* h, const float* d_x, const float* d_disp, float* d_lr_out,

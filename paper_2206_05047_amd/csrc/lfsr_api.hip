@@ -283,13 +283,18 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   // z/w-steps of both blocks; e and the NLTV divergence feed v
   timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_wzd(g, h->disp, h->y, s, b); });
   if (g.sd > 0) timed(h, LFSR_K_NLTV, s, [&] { launch_tv(g, s, b); });
-  timed(h, LFSR_K_ADJOINT, s, [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm, forward_blocks(g)); });
+  timed(h, LFSR_K_ADJOINT, s, [&] {
+    launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm, forward_blocks(g));
+    launch_merge(g, b.r, s, b, kGateAdmm);
+  });
   timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b); });
   // x-step: K CG steps on G^T G delta = -v, accumulated straight into the FP32 estimate
   for (int k = 1; k <= h->prm.cg_iters; ++k) {
     timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_cg(g, b.pv, h->disp, s, b, kGateAdmm | kGateCg); });
-    timed(h, LFSR_K_ADJOINT, s,
-          [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g)); });
+    timed(h, LFSR_K_ADJOINT, s, [&] {
+      launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g));
+      launch_merge(g, b.hp, s, b, kGateAdmm | kGateCg);
+    });
     timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgupd(g, k, s, b); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });
@@ -520,7 +525,7 @@ lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp,
   const Geom& g = h->plan.g;
   const int npmax = launch_absmax(g, d_lr, (long long)g.sk * g.q, S(hip_stream), h->b);
   launch_adjoint(g, d_lr, kStF32, d_disp, S(hip_stream), h->b, 0, npmax);
-  launch_merge(g, d_hr_out, S(hip_stream), h->b);
+  launch_merge(g, d_hr_out, S(hip_stream), h->b, 0);
   return check_hip(h, "lfsr_adjoint");
 }
 
@@ -529,10 +534,12 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   lfsr_status st = usable(h);
   if (st) return st;
   if (!d_p || !d_disp || !d_m || !d_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  if (d_out == d_p || d_out == d_m) return set_err(h, LFSR_EINVAL, "d_out must not alias d_p or d_m");
   const Geom& g = h->plan.g;
   hipStream_t s = S(hip_stream);
   launch_forward_cg(g, d_p, d_disp, s, h->b, 0);
   launch_adjoint(g, h->b.lr, h->b.st, d_disp, s, h->b, 0, forward_blocks(g));
+  launch_merge(g, d_out, s, h->b, 0);
   launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0);
   return check_hip(h, "lfsr_normal");
 }

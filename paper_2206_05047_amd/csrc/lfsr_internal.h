@@ -138,8 +138,10 @@ void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp,
                     int gate, int npmax);
 int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b);
 int forward_blocks(const Geom& g);
-void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b);
+// dense A^T e from the adjoint's partial images
+void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b, int gate);
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b);
+// out: merged A^T A pv on entry, H pv on exit
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot);
 void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b);

@@ -37,6 +37,15 @@ __device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
 
 __device__ __forceinline__ float clipf(float u, float c) { return fminf(fmaxf(u, -c), c); }
 
+// floor(v) as an integer in one instruction (v_cvt_flr_i32_f32); with
+// __builtin_amdgcn_fractf (v_fract_f32: v - floor(v), kept below 1) a warp
+// coordinate splits into cell and bilinear weight in two instructions
+__device__ __forceinline__ int floor_i(float v) {
+  int r;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -330,8 +339,47 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
 // lattice columns from a wave-private LDS row buffer.  ZETA, KB and TLY are
 // compile-time so that the position walk and the tap selection unroll.
 // grid = (ceil(sx/f_tlx), ceil(sy/TLY), ceil(sk/f_vpb)).
+// The position walk of k_fwdcol for NV views at once: warp every blur
+// position of the lane's column and accumulate the vertical blur at the TLY
+// lattice rows.  (NV = 1 in use: two interleaved views need more registers
+// than the walk can hold without spilling.)
+template <int NV, int NY, int TLY, int ZETA, int KB>
+__device__ __forceinline__ void fwd_walk(const Geom& g, const float* __restrict__ xs, const float (&om)[NY],
+                                         int cbase, int SX, const float (&tau)[NV], const float (&rho)[NV],
+                                         float (&acc)[NV][TLY]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int i = 0; i < TLY; ++i) acc[v][i] = 0.f;
+#pragma unroll
+  for (int py = 0; py < NY; ++py) {
+    float val[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const float sy = tau[v] * om[py], sx = rho[v] * om[py];
+      const float fy0 = floorf(sy), fx0 = floorf(sx);
+      const float fy = sy - fy0, fx = sx - fx0;
+      // |row| < 2^23: the 24-bit multiply is exact
+      const int off = cbase + __mul24(py + (int)fy0, SX) + (int)fx0;
+      const float a = xs[off], b = xs[off + 1], c = xs[off + SX], d = xs[off + SX + 1];
+      const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
+      val[v] = fmaf(fy, bot - top, top);
+    }
+    // the lattice rows i this position reaches: 0 <= py - i ZETA < KB
+#pragma unroll
+    for (int j = 0; j < (KB + ZETA - 1) / ZETA; ++j) {
+      const int i = py / ZETA - j;
+      const int t = py - i * ZETA;  // compile-time after unrolling
+      if (i >= 0 && i < TLY && t < KB) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v][i] = fmaf(g.g[t], val[v], acc[v][i]);
+      }
+    }
+  }
+}
+
 template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO>
-__global__ __launch_bounds__(kThreads) void k_fwdcol(Geom g, const TS* __restrict__ src,
+__global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
                                                      const float* __restrict__ disp, TO* __restrict__ out,
                                                      const float* __restrict__ y, TO* __restrict__ wD,
                                                      double* __restrict__ part, float* __restrict__ pmax,
@@ -386,37 +434,10 @@ __global__ __launch_bounds__(kThreads) void k_fwdcol(Geom g, const TS* __restric
   float vmax = 0.f;
   const int k0 = blockIdx.z * g.f_vpb;
   const int k1 = min(g.sk, k0 + g.f_vpb);
-  for (int k = k0 + wave; k < k1; k += 4) {
-    const int ka = k / g.V, kc = k - ka * g.V;
-    const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
+  // horizontal blur at the lattice columns and the epilogue of one view
+  auto finish = [&](const float (&acc)[TLY], int k, const float (&yv)[NO], const float (&w0)[NO])
+                    __attribute__((always_inline)) {
     const size_t vo = (size_t)k * g.q;
-    float yv[NO], w0[NO];
-    if constexpr (WZD) {  // issued early; consumed after the position walk
-#pragma unroll
-      for (int s = 0; s < NO; ++s) {
-        yv[s] = y[vo + oofs[s]];
-        w0[s] = (float)wD[vo + oofs[s]];
-      }
-    }
-    float acc[TLY];
-#pragma unroll
-    for (int i = 0; i < TLY; ++i) acc[i] = 0.f;
-#pragma unroll
-    for (int py = 0; py < NY; ++py) {
-      const float sy = tau * om[py], sx = rho * om[py];
-      const float fy0 = floorf(sy), fx0 = floorf(sx);
-      const float fy = sy - fy0, fx = sx - fx0;
-      // |row| < 2^23: the 24-bit multiply is exact
-      const int off = cbase + __mul24(py + (int)fy0, SX) + (int)fx0;
-      const float a = xs[off], b = xs[off + 1], c = xs[off + SX], d = xs[off + SX + 1];
-      const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
-      const float val = fmaf(fy, bot - top, top);
-#pragma unroll
-      for (int i = 0; i < TLY; ++i) {
-        const int t = py - i * ZETA;  // tap of lattice row i (compile-time after unrolling)
-        if (t >= 0 && t < KB) acc[i] = fmaf(g.g[t], val, acc[i]);
-      }
-    }
     if (colok) {
 #pragma unroll
       for (int i = 0; i < TLY; ++i) vb[i * NX + px] = acc[i];
@@ -448,7 +469,27 @@ __global__ __launch_bounds__(kThreads) void k_fwdcol(Geom g, const TS* __restric
         s_dw += dw * dw;
       }
     }
-    __builtin_amdgcn_wave_barrier();  // reads of vb complete before the next view overwrites it
+    __builtin_amdgcn_wave_barrier();  // reads of vb complete before it is written again
+  };
+  auto load_wzd = [&](int k, float (&yv)[NO], float (&w0)[NO]) __attribute__((always_inline)) {
+    if constexpr (WZD) {  // issued early; consumed after the position walk
+      const size_t vo = (size_t)k * g.q;
+#pragma unroll
+      for (int s = 0; s < NO; ++s) {
+        yv[s] = y[vo + oofs[s]];
+        w0[s] = (float)wD[vo + oofs[s]];
+      }
+    }
+  };
+  for (int k = k0 + wave; k < k1; k += 4) {
+    const int ka = k / g.V, kc = k - ka * g.V;
+    float yv[NO], w0[NO];
+    load_wzd(k, yv, w0);
+    const float tau[1] = {(float)(ka - (g.U - 1) / 2)};
+    const float rho[1] = {(float)(kc - (g.V - 1) / 2)};
+    float acc[1][TLY];
+    fwd_walk<1, NY, TLY, ZETA, KB>(g, xs, om, cbase, SX, tau, rho, acc);
+    finish(acc[0], k, yv, w0);
   }
   const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   {
@@ -845,12 +886,11 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
       }
       u = (colin && Y0 + r < g.H) ? u : 0.f;
       const float sy = tau * om[r], sx = rho * om[r];
-      const float fy0 = floorf(sy), fx0 = floorf(sx);
-      const float wy1 = sy - fy0, wx1 = sx - fx0;
+      const float wy1 = __builtin_amdgcn_fractf(sy), wx1 = __builtin_amdgcn_fractf(sx);
       const float u1 = u * wy1, u0 = u - u1;
       const float br = u1 * wx1, bl = u1 - br, tr = u0 * wx1, tl = u0 - tr;
       // W_k^T: the four cells W_k read (two row bases, +1 column as an immediate offset)
-      unsigned long long* c0 = acc + __mul24(r + h + (int)fy0, EX) + (x + h + (int)fx0);
+      unsigned long long* c0 = acc + __mul24(r + h + floor_i(sy), EX) + (x + h + floor_i(sx));
       unsigned long long* c1 = c0 + EX;
       atomicAdd(c0, (unsigned long long)(long long)(int)tl);
       atomicAdd(c0 + 1, (unsigned long long)(long long)(int)tr);
@@ -877,8 +917,11 @@ __global__ __launch_bounds__(kThreads) void k_absmax(const float* __restrict__ v
   if (threadIdx.x == 0) pmax[blockIdx.x] = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
 }
 
-// out = sum of the adjoint partial images (the operator entry point).
-__global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restrict__ adj, float* __restrict__ out) {
+// out = sum of the adjoint partial images (dense A^T e, read by the CG
+// kernels and returned by the operator entry point).
+__global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restrict__ adj, float* __restrict__ out,
+                                                    const DevScalars* __restrict__ sc, int gate) {
+  if (gated(sc, g, gate)) return;
   for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
     const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
     out[o] = adj_merge(g, adj, Y, X);
@@ -1019,8 +1062,10 @@ __device__ __forceinline__ float tv_laplacian(const Geom& g, const float* __rest
   return lap;
 }
 
+// `hp` holds the merged A^T A p on entry and H p on exit (read, then written,
+// by the same thread).
 __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict__ pv, const float* __restrict__ m,
-                                                 const float* __restrict__ adj, float* __restrict__ hp,
+                                                 float* hp,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc,
                                                  int gate, int with_dot) {
   if (gated(sc, g, gate)) return;
@@ -1052,7 +1097,7 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
       const int sl = (ly + rw) * LXd + (lx + rw);
       lap = interior ? tv_laplacian<true>(g, ps, m2, sl, Y, X, LXd) : tv_laplacian<false>(g, ps, m2, sl, Y, X, LXd);
     }
-    const float v = g.cA * adj_merge(g, adj, Y, X) + g.half_theta * lap;
+    const float v = g.cA * hp[o] + g.half_theta * lap;
     hp[o] = v;
     if (with_dot) s_dot += (double)pv[o] * (double)v;
   }
@@ -1066,8 +1111,8 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
 // CG start (Algorithm 2 from delta = 0): v = A^T e + (vartheta/2) S^T f,
 // r = -v, p = r, partials of <r, r>.  Block 0 also closes the wz-step's
 // statistics: J(x^(n-1)), the primal residual and the stop test.
-__global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __restrict__ adj,
-                                                     const float* __restrict__ vs, float* __restrict__ r,
+// `r` holds the merged A^T e on entry.
+__global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __restrict__ vs, float* r,
                                                      float* __restrict__ pv, double* __restrict__ prr,
                                                      const double* __restrict__ pwzd, int nwzd,
                                                      const double* __restrict__ ptv, int ntv,
@@ -1082,8 +1127,7 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
       const long long o = o0 + j * kThreads;
       v[j] = 0.f;
       if (o < g.p) {
-        const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
-        v[j] = adj_merge(g, adj, Y, X);
+        v[j] = r[o];
         if (g.sd > 0) v[j] += g.half_theta * vs[o];
       }
     }
@@ -1411,7 +1455,7 @@ static constexpr bool fwdcol_shape(int zeta, int kb) {
   return (zeta == 2 && (kb == 3 || kb == 5 || kb == 7 || kb == 9)) || (zeta == 3 && (kb == 5 || kb == 7 || kb == 9)) ||
          (zeta == 4 && (kb == 7 || kb == 9));
 }
-static constexpr int fwdcol_tly(int zeta, int kb) { return 15 * zeta + kb <= 64 ? 16 : 8; }
+static constexpr int fwdcol_tly(int zeta, int kb) { return (void)zeta, (void)kb, 8; }
 
 bool forward_col_setup(Geom& g) {
   if (!fwdcol_shape(g.zeta, g.kb)) return false;
@@ -1625,8 +1669,9 @@ int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, con
 
 int forward_blocks(const Geom& g) { return nblocks(forward_grid(g)); }
 
-void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_merge, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, (const float*)b.adj, out);
+void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b, int gate) {
+  hipLaunchKernelGGL(k_merge, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, (const float*)b.adj, out,
+                     (const DevScalars*)b.sc, gate);
 }
 
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
@@ -1639,13 +1684,13 @@ void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
 
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot) {
-  hipLaunchKernelGGL(k_hp, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, (const float*)b.adj, out, b.p_php,
+  hipLaunchKernelGGL(k_hp, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php,
                      (const DevScalars*)b.sc, gate, with_dot);
 }
 
 void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_cginit, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.adj,
-                     (const float*)b.vs, b.r, b.pv, b.p_rr[0], (const double*)b.p_wzd, nblocks(forward_grid(g)),
+  hipLaunchKernelGGL(k_cginit, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.vs, b.r, b.pv,
+                     b.p_rr[0], (const double*)b.p_wzd, nblocks(forward_grid(g)),
                      (const double*)b.p_tv, nblocks(tv_grid(g)), b.stats, b.sc);
 }
 
