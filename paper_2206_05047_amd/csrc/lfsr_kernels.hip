@@ -846,6 +846,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   }
   __syncthreads();  // accumulator zeroed
 
+  const int cb0 = h * EX + x + h;  // accumulator cell of (row 0, this column)
   for (; k < k1; k += 4) {
 #pragma unroll
     for (int s = 0; s < ESL; ++s)
@@ -884,13 +885,14 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
           if (t <= 2 * RB) u = fmaf(g.g[t], hrow[qr + lo + m + CF], u);
         }
       }
-      u = (colin && Y0 + r < g.H) ? u : 0.f;
+      // (pixels outside the image have zero disparity, so they only reach
+      // accumulator cells outside the image, which the merge never reads)
       const float sy = tau * om[r], sx = rho * om[r];
       const float wy1 = __builtin_amdgcn_fractf(sy), wx1 = __builtin_amdgcn_fractf(sx);
       const float u1 = u * wy1, u0 = u - u1;
       const float br = u1 * wx1, bl = u1 - br, tr = u0 * wx1, tl = u0 - tr;
       // W_k^T: the four cells W_k read (two row bases, +1 column as an immediate offset)
-      unsigned long long* c0 = acc + __mul24(r + h + floor_i(sy), EX) + (x + h + floor_i(sx));
+      unsigned long long* c0 = acc + (__mul24(floor_i(sy), EX) + floor_i(sx)) + (cb0 + r * EX);
       unsigned long long* c1 = c0 + EX;
       atomicAdd(c0, (unsigned long long)(long long)(int)tl);
       atomicAdd(c0 + 1, (unsigned long long)(long long)(int)tr);
@@ -936,12 +938,24 @@ __global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restr
 // The second term is pulled: f_d(z-d) is recomputed from the previous dual,
 // which ping-pong buffers keep intact.  Per-block partials {sum|g|,
 // sum (w_S'-w_S)^2} go to `part`.  grid = (ceil(W/64), ceil(H/16)).
-template <bool INTERIOR, typename T>
+// Offset d of a (2 rw + 1)^2 NLTV window, row-major with the centre skipped
+// (the host builds the weight tables in the same order).
+__host__ __device__ constexpr int win_dy(int rw, int d) {
+  return (d < ((2 * rw + 1) * (2 * rw + 1)) / 2 ? d : d + 1) / (2 * rw + 1) - rw;
+}
+__host__ __device__ constexpr int win_dx(int rw, int d) {
+  return (d < ((2 * rw + 1) * (2 * rw + 1)) / 2 ? d : d + 1) % (2 * rw + 1) - rw;
+}
+
+// RW > 0: compile-time window radius (offsets and tile pitch become
+// immediates); RW = 0: the radius and offsets come from g at run time.
+template <bool INTERIOR, typename T, int RW>
 __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__ xs, const float* __restrict__ ms,
                                         const T* wo, T* wn_, float* __restrict__ vs, int X0, int Y0,
                                         double& s_abs, double& s_dw) {
-  const int rw = g.rw;
+  const int rw = RW > 0 ? RW : g.rw;
   const int LXd = kTvTileX + 2 * rw;
+  const int SD = RW > 0 ? (2 * RW + 1) * (2 * RW + 1) - 1 : g.sd;
   const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
   const int X = X0 + lx;
   int Y[4], sl[4];
@@ -956,8 +970,8 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   // software pipeline: the dual values of offsets d+1 and d+2 are in flight while d is used
   float c0[4], c2[4], n0[4], n2[4];
-  auto load = [&](int d, float (&w0)[4], float (&w2)[4]) {
-    const int dy = g.ody[d], dx = g.odx[d];
+  auto load = [&](int d, float (&w0)[4], float (&w2)[4]) __attribute__((always_inline)) {
+    const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const T* wd = wo + (size_t)d * g.p;
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -967,9 +981,11 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
       w2[rr] = bin ? (float)wd[o - (ptrdiff_t)dy * g.W - dx] : 0.f;
     }
   };
-  if (g.sd > 0) load(0, c0, c2);
-  if (g.sd > 1) load(1, n0, n2);
-  for (int d = 0; d < g.sd; ++d) {
+  if (SD > 0) load(0, c0, c2);
+  if (SD > 1) load(1, n0, n2);
+  // kept rolled: unrolling lets the compiler hoist every dual load and spill
+#pragma unroll 1
+  for (int d = 0; d < SD; ++d) {
     float w0[4], w2[4];
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -978,8 +994,8 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
       c0[rr] = n0[rr];
       c2[rr] = n2[rr];
     }
-    if (d + 2 < g.sd) load(d + 2, n0, n2);
-    const int dy = g.ody[d], dx = g.odx[d];
+    if (d + 2 < SD) load(d + 2, n0, n2);
+    const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const int dd = dy * LXd + dx;
     const float c = g.cd[d];
     T* wnd = wn_ + (size_t)d * g.p;
@@ -1011,13 +1027,13 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
 
 // T: storage type of x and of the dual; the dual recomputed for the pulled
 // term is the same FP32 value the owning thread stores (rounded) for w_S'.
-template <typename T>
+template <typename T, int RW>
 __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
                                                  T* ws0, T* ws1, float* __restrict__ vs,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
   extern __shared__ float smem[];
-  const int rw = g.rw;
+  const int rw = RW > 0 ? RW : g.rw;
   const int LXd = kTvTileX + 2 * rw, LYd = kTvTileY + 2 * rw;
   float* xs = smem;
   float* ms = xs + LYd * LXd;
@@ -1029,8 +1045,8 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x
   T* wn_ = sc->wcur ? ws0 : ws1;
   const bool interior = X0 - rw >= 0 && X0 + kTvTileX + rw <= g.W && Y0 - rw >= 0 && Y0 + kTvTileY + rw <= g.H;
   double s_abs = 0.0, s_dw = 0.0;
-  if (interior) tv_tile<true, T>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
-  else tv_tile<false, T>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  if (interior) tv_tile<true, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  else tv_tile<false, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
   double v[2] = {s_abs, s_dw};
   block_sum<2>(v);
   if (threadIdx.x == 0) {
@@ -1046,14 +1062,15 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x
 //   sum_d c_d^2 (m(z)^2 + m(z+d)^2) (p(z) - p(z+d)) 1(z+d in the image),
 // which equals S^T V^2 S p because the offset set is symmetric.  With
 // with_dot, per-block partials of <p, Hp> go to `part`.
-template <bool INTERIOR>
+template <bool INTERIOR, int RW>
 __device__ __forceinline__ float tv_laplacian(const Geom& g, const float* __restrict__ ps,
                                               const float* __restrict__ m2, int sl, int Y, int X, int LXd) {
   const float pz = ps[sl], mz = m2[sl];
   float lap = 0.f;
-#pragma unroll 8
-  for (int d = 0; d < g.sd; ++d) {
-    const int dy = g.ody[d], dx = g.odx[d];
+  const int SD = RW > 0 ? (2 * RW + 1) * (2 * RW + 1) - 1 : g.sd;
+#pragma unroll(RW > 0 ? 64 : 8)
+  for (int d = 0; d < SD; ++d) {
+    const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const int sn = sl + dy * LXd + dx;
     float t = g.cd2[d] * (mz + m2[sn]) * (pz - ps[sn]);
     if (!INTERIOR && (Y + dy < 0 || Y + dy >= g.H || X + dx < 0 || X + dx >= g.W)) t = 0.f;
@@ -1064,13 +1081,14 @@ __device__ __forceinline__ float tv_laplacian(const Geom& g, const float* __rest
 
 // `hp` holds the merged A^T A p on entry and H p on exit (read, then written,
 // by the same thread).
+template <int RW>
 __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict__ pv, const float* __restrict__ m,
                                                  float* hp,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc,
                                                  int gate, int with_dot) {
   if (gated(sc, g, gate)) return;
   extern __shared__ float smem[];
-  const int rw = g.rw;
+  const int rw = RW > 0 ? RW : g.rw;
   const int LXd = kTvTileX + 2 * rw, LYd = kTvTileY + 2 * rw;
   float* ps = smem;
   float* m2 = ps + LYd * LXd;
@@ -1095,7 +1113,8 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
     float lap = 0.f;
     if (g.sd > 0) {
       const int sl = (ly + rw) * LXd + (lx + rw);
-      lap = interior ? tv_laplacian<true>(g, ps, m2, sl, Y, X, LXd) : tv_laplacian<false>(g, ps, m2, sl, Y, X, LXd);
+      lap = interior ? tv_laplacian<true, RW>(g, ps, m2, sl, Y, X, LXd)
+                     : tv_laplacian<false, RW>(g, ps, m2, sl, Y, X, LXd);
     }
     const float v = g.cA * hp[o] + g.half_theta * lap;
     hp[o] = v;
@@ -1677,15 +1696,31 @@ void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b, int g
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
   by_storage(b.st, [&](auto* tag) {
     using T = LFSR_ELEM(tag);
-    hipLaunchKernelGGL(k_tv<T>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m,
-                       (T*)b.wS[0], (T*)b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc);
+#define LFSR_TV(R)                                                                                                 \
+  hipLaunchKernelGGL((k_tv<T, R>), tv_grid(g), dim3(kThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m, \
+                     (T*)b.wS[0], (T*)b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc)
+    switch (g.rw) {
+      case 1: LFSR_TV(1); break;
+      case 2: LFSR_TV(2); break;
+      case 3: LFSR_TV(3); break;
+      default: LFSR_TV(0); break;
+    }
+#undef LFSR_TV
   });
 }
 
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot) {
-  hipLaunchKernelGGL(k_hp, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php,
-                     (const DevScalars*)b.sc, gate, with_dot);
+#define LFSR_HP(R)                                                                                              \
+  hipLaunchKernelGGL(k_hp<R>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php, \
+                     (const DevScalars*)b.sc, gate, with_dot)
+  switch (g.rw) {
+    case 1: LFSR_HP(1); break;
+    case 2: LFSR_HP(2); break;
+    case 3: LFSR_HP(3); break;
+    default: LFSR_HP(0); break;
+  }
+#undef LFSR_HP
 }
 
 void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b) {
