@@ -226,6 +226,8 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
     pl->off_prr1 = take((size_t)kRedBlocks * sizeof(double));
     pl->off_pphp = take((size_t)tg.x * tg.y * sizeof(double));
     pl->off_pmax = take(std::max((size_t)fg.x * fg.y * fg.z, (size_t)kRedBlocks) * sizeof(float));
+    const dim3 ag = adjoint_grid(g);
+    pl->off_pcnt = take((size_t)ag.x * ag.y * ag.z * sizeof(int));
   }
   pl->off_stats = take((size_t)p->admm_iters * LFSR_NSTAT * sizeof(double));
   pl->bytes = o;
@@ -355,6 +357,7 @@ lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, l
   h->b.p_rr[1] = (double*)(w + pl.off_prr1);
   h->b.p_php = (double*)(w + pl.off_pphp);
   h->b.p_max = (float*)(w + pl.off_pmax);
+  h->b.p_cnt = (int*)(w + pl.off_pcnt);
   h->b.stats = (double*)(w + pl.off_stats);
   h->n_done = 0;
   h->bound = false;
@@ -384,6 +387,7 @@ lfsr_status lfsr_init(lfsr_handle* h, const float* d_lr, const float* d_disp, co
   h->occ = d_occ;
   launch_reset(0, s, h->b);
   launch_check(g, d_lr, d_disp, d_occ, s, h->b);
+  launch_adjcount(g, d_disp, s, h->b);
   launch_zero(h->b.wD, h->b.st, (long long)g.sk * g.q, s);
   launch_zero(h->b.wS[0], h->b.st, (long long)g.sd * g.p, s);
   launch_fill(h->b.m, g.p, 1.f, s);
@@ -524,6 +528,7 @@ lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp,
   if (!d_lr || !d_disp || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
   const Geom& g = h->plan.g;
   const int npmax = launch_absmax(g, d_lr, (long long)g.sk * g.q, S(hip_stream), h->b);
+  launch_adjcount(g, d_disp, S(hip_stream), h->b);
   launch_adjoint(g, d_lr, kStF32, d_disp, S(hip_stream), h->b, 0, npmax);
   launch_merge(g, d_hr_out, S(hip_stream), h->b, 0);
   return check_hip(h, "lfsr_adjoint");
@@ -538,6 +543,7 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   const Geom& g = h->plan.g;
   hipStream_t s = S(hip_stream);
   launch_forward_cg(g, d_p, d_disp, s, h->b, 0);
+  launch_adjcount(g, d_disp, s, h->b);
   launch_adjoint(g, h->b.lr, h->b.st, d_disp, s, h->b, 0, forward_blocks(g));
   launch_merge(g, d_out, s, h->b, 0);
   launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0);

@@ -98,6 +98,7 @@ struct Bufs {
   double* p_rr[2]; // [red_blocks] <r,r> partials (ping-pong over CG steps)
   double* p_php;   // [tv blocks] <p,Hp> partials
   float* p_max;    // [max(forward blocks, kRedBlocks)] per-block max |LR| (adjoint fixed-point scale)
+  int* p_cnt;      // [adjoint blocks] most contributions any accumulator cell of the block receives
   double* stats;   // [n_iter][6]
   DevScalars* sc;
 };
@@ -137,6 +138,10 @@ void launch_forward_wzd(const Geom& g, const float* disp, const float* y, hipStr
 void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp, hipStream_t s, const Bufs& b,
                     int gate, int npmax);
 int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, const Bufs& b);
+// contribution counts of the column adjoint for a disparity map (b.p_cnt);
+// must run before launch_adjoint whenever the disparity changes (no-op for
+// the general adjoint)
+void launch_adjcount(const Geom& g, const float* disp, hipStream_t s, const Bufs& b);
 int forward_blocks(const Geom& g);
 // dense A^T e from the adjoint's partial images
 void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b, int gate);

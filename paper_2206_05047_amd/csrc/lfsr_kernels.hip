@@ -45,6 +45,12 @@ __device__ __forceinline__ int floor_i(float v) {
   asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(v));
   return r;
 }
+// round to nearest (halves up) as an integer in one instruction (v_cvt_rpi_i32_f32)
+__device__ __forceinline__ int round_i(float v) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -739,9 +745,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
 // ---------------------------------------------------------------------------
 // Adjoint, column-per-lane form (same operator as k_adjoint).  A block owns an
 // HR tile of adjcol_th(ZETA) rows x adjcol_tw(ZETA) columns plus the warp
-// halo, in a shared 64-bit fixed-point accumulator (as in k_adjoint); its
-// four waves take views k0 + wave, k0 + wave + 4, ... of the block's view
-// group.  Lane x owns tile column x and walks the tile rows: B^T D^T is a
+// halo, in a shared 32-bit fixed-point accumulator; its four waves take views
+// k0 + wave, k0 + wave + 4, ... of the block's view group.  Fixed point: a
+// count pass (k_adjcount, once per disparity map) records the most
+// contributions n any cell of the block receives; every contribution is at
+// most M = max |lr| in magnitude, so with S = 2^(30 - ceil log2(n + 1) -
+// ceil log2 M) each scaled contribution stays below 2^(30 - hd) and the
+// exact integer sum of a cell below 2^30: the int32 wrap-around of
+// intermediate sums cancels, and integer addition keeps the result bitwise
+// reproducible.  Contributions are rounded to nearest (no bias).  Lane x owns tile column x and walks the tile rows: B^T D^T is a
 // horizontal polyphase pass per staged LR row (three LDS reads) followed by a
 // vertical pass in registers with compile-time taps, so a pixel costs a
 // fraction of an LDS read instead of several; then W_k^T sends u to the four
@@ -756,6 +768,7 @@ template <int ZETA, int KB, typename TI>
 __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restrict__ lr,
                                                      const float* __restrict__ disp, float* __restrict__ outp,
                                                      const float* __restrict__ pmax, int npmax,
+                                                     const int* __restrict__ pcnt,
                                                      const DevScalars* __restrict__ sc, int gate) {
   if (gated(sc, g, gate)) return;
   constexpr int RB = KB / 2;
@@ -765,12 +778,12 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   constexpr int LX = (TW - 1 + RB) / ZETA + CF + 1;  // staged LR columns
   constexpr int ESL = (RL * LX + 63) / 64;
   constexpr int MM = (2 * RB) / ZETA + 1;            // taps per polyphase phase (at most)
-  extern __shared__ long long smem8[];
+  extern __shared__ float smem[];
   const int h = g.halo, EY = g.a_ey, EX = g.a_ex;  // EY = TH + 2h, EX = TW + 2h
-  unsigned long long* acc = reinterpret_cast<unsigned long long*>(smem8);
+  unsigned* acc = reinterpret_cast<unsigned*>(smem);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float* e_ = reinterpret_cast<float*>(smem8 + EY * EX) + wave * (RL * LX);  // wave-private LR rows
-  for (int i = tid; i < EY * EX; i += kThreads) acc[i] = 0;
+  float* e_ = smem + EY * EX + wave * (RL * LX);  // wave-private LR rows
+  for (int i = tid; i < EY * EX; i += kThreads) acc[i] = 0u;
 
   // fixed-point scale from the producer's block maxima (order-free, so exact)
   float mloc = 0.f;
@@ -781,9 +794,11 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   if (lane == 0) smax[wave] = mloc;
   __syncthreads();
   const float M = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
-  int eM = 0;
+  int eM = 0, hd = 0;
   if (M > 0.f) (void)frexpf(M, &eM);  // M < 2^eM
-  const int sexp = min(max(30 - eM, -120), 120);
+  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  (void)frexpf((float)pcnt[bid] + 1.f, &hd);  // n + 1 <= 2^hd
+  const int sexp = min(max(30 - hd - eM, -120), 120);
   const float S = ldexpf(1.f, sexp), invS = ldexpf(1.f, -sexp);
 
   const int Y0 = blockIdx.y * TH, X0 = blockIdx.x * TW;  // tile origin (multiples of ZETA)
@@ -892,18 +907,72 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
       const float u1 = u * wy1, u0 = u - u1;
       const float br = u1 * wx1, bl = u1 - br, tr = u0 * wx1, tl = u0 - tr;
       // W_k^T: the four cells W_k read (two row bases, +1 column as an immediate offset)
-      unsigned long long* c0 = acc + (__mul24(floor_i(sy), EX) + floor_i(sx)) + (cb0 + r * EX);
-      unsigned long long* c1 = c0 + EX;
-      atomicAdd(c0, (unsigned long long)(long long)(int)tl);
-      atomicAdd(c0 + 1, (unsigned long long)(long long)(int)tr);
-      atomicAdd(c1, (unsigned long long)(long long)(int)bl);
-      atomicAdd(c1 + 1, (unsigned long long)(long long)(int)br);
+      unsigned* c0 = acc + (__mul24(floor_i(sy), EX) + floor_i(sx)) + (cb0 + r * EX);
+      unsigned* c1 = c0 + EX;
+      atomicAdd(c0, (unsigned)round_i(tl));
+      atomicAdd(c0 + 1, (unsigned)round_i(tr));
+      atomicAdd(c1, (unsigned)round_i(bl));
+      atomicAdd(c1 + 1, (unsigned)round_i(br));
     }
   }
   __syncthreads();
   const size_t tiles = (size_t)g.a_nty * g.a_ntx;
   float* o = outp + ((size_t)blockIdx.z * tiles + (size_t)blockIdx.y * g.a_ntx + blockIdx.x) * (size_t)(EY * EX);
-  for (int idx = tid; idx < EY * EX; idx += kThreads) o[idx] = (float)(long long)acc[idx] * invS;
+  for (int idx = tid; idx < EY * EX; idx += kThreads) o[idx] = (float)(int)acc[idx] * invS;
+}
+
+// Contribution counts of k_adjcol: the same tiles, view groups and targets,
+// each of the four cells of every (view, pixel) counted once; pcnt[block] =
+// the largest count of any cell.  Depends on the disparity map only.
+template <int ZETA, int KB>
+__global__ __launch_bounds__(kThreads) void k_adjcount(Geom g, const float* __restrict__ disp, int* __restrict__ pcnt) {
+  constexpr int TW = adjcol_tw(ZETA), TH = adjcol_th(ZETA);
+  extern __shared__ float smem[];
+  const int h = g.halo, EY = g.a_ey, EX = g.a_ex;
+  unsigned* cnt = reinterpret_cast<unsigned*>(smem);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int i = tid; i < EY * EX; i += kThreads) cnt[i] = 0u;
+  const int Y0 = blockIdx.y * TH, X0 = blockIdx.x * TW;
+  const bool own = lane < TW;
+  const int x = own ? lane : 0;
+  const int X = X0 + x;
+  float om[TH];
+#pragma unroll
+  for (int r = 0; r < TH; ++r) {
+    const int Y = Y0 + r;
+    const bool in = own && X < g.W && Y < g.H;
+    om[r] = disp[in ? (size_t)Y * g.W + X : 0];
+    om[r] = in ? fminf(fmaxf(om[r], -g.disp_bound), g.disp_bound) : 0.f;
+  }
+  __syncthreads();
+  const int k0 = blockIdx.z * g.a_vpb, k1 = min(g.sk, k0 + g.a_vpb);
+  const int cb0 = h * EX + x + h;
+  if (own) {
+    for (int k = k0 + wave; k < k1; k += 4) {
+      const int ka = k / g.V, kc = k - ka * g.V;
+      const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
+#pragma unroll
+      for (int r = 0; r < TH; ++r) {
+        const float sy = tau * om[r], sx = rho * om[r];
+        unsigned* c0 = cnt + (__mul24(floor_i(sy), EX) + floor_i(sx)) + (cb0 + r * EX);
+        atomicAdd(c0, 1u);
+        atomicAdd(c0 + 1, 1u);
+        atomicAdd(c0 + EX, 1u);
+        atomicAdd(c0 + EX + 1, 1u);
+      }
+    }
+  }
+  __syncthreads();
+  unsigned m = 0;
+  for (int i = tid; i < EY * EX; i += kThreads) m = max(m, cnt[i]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off, 64));
+  __shared__ unsigned sm[4];
+  if (lane == 0) sm[wave] = m;
+  __syncthreads();
+  if (tid == 0)
+    pcnt[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] =
+        (int)max(max(sm[0], sm[1]), max(sm[2], sm[3]));
 }
 
 // Per-block max |v| of n floats (scale input of the adjoint entry point).
@@ -1509,7 +1578,7 @@ size_t adjoint_lds(const Geom& g) {
   if (g.a_col) {
     const int z = g.zeta, CF = g.rb / z;
     const int RL = (g.a_th - 1 + g.rb) / z + CF + 1, LXc = (g.a_tw - 1 + g.rb) / z + CF + 1;
-    return 8 * (size_t)g.a_ey * g.a_ex + sizeof(float) * 4 * (size_t)RL * LXc;
+    return 4 * (size_t)g.a_ey * g.a_ex + sizeof(float) * 4 * (size_t)RL * LXc;
   }
   int ci, LY, LX, MM, PAD;
   adj_dims(g, ci, LY, LX, MM, PAD);
@@ -1559,14 +1628,14 @@ bool adjoint_col_setup(Geom& g) {
   // ceil(blocks / resident slots) rounds, and every extra group adds a set of
   // partial images to merge; pick the group count with the lowest estimate
   long long per_cu = (long long)((160 * 1024) / lds);
-  if (per_cu > 5) per_cu = 5;
+  if (per_cu > 4) per_cu = 4;  // ~110 VGPRs: four waves per SIMD
   if (per_cu < 1) per_cu = 1;
   const long long slots = 256 * per_cu, tiles = (long long)t.a_nty * t.a_ntx;
   int best_g = 1;
   double best = 1e30;
   for (int G = 1; G <= 8 && G <= g.sk; ++G) {
     const double rounds = (double)((tiles * G + slots - 1) / slots);
-    const double cost = rounds / G + 0.02 * G;
+    const double cost = rounds / G + 0.05 * G;
     if (cost < best - 1e-12) {
       best = cost;
       best_g = G;
@@ -1657,7 +1726,7 @@ void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp,
     if (g.a_col) {
 #define LFSR_ADC(Z, K)                                                                                          \
   if (g.zeta == Z && g.kb == K) {                                                                               \
-    hipLaunchKernelGGL((k_adjcol<Z, K, T>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, sc, gate);        \
+    hipLaunchKernelGGL((k_adjcol<Z, K, T>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, b.p_cnt, sc, gate); \
     return;                                                                                                     \
   }
       LFSR_ADC(2, 3) LFSR_ADC(2, 5) LFSR_ADC(2, 7) LFSR_ADC(2, 9) LFSR_ADC(3, 5) LFSR_ADC(3, 7) LFSR_ADC(3, 9)
@@ -1687,6 +1756,20 @@ int launch_absmax(const Geom& g, const float* v, long long n, hipStream_t s, con
 }
 
 int forward_blocks(const Geom& g) { return nblocks(forward_grid(g)); }
+
+void launch_adjcount(const Geom& g, const float* disp, hipStream_t s, const Bufs& b) {
+  if (!g.a_col) return;
+  const dim3 grid = adjoint_grid(g), blk(kThreads);
+  const size_t lds = 4 * (size_t)g.a_ey * g.a_ex;
+#define LFSR_CNT(Z, K)                                                                   \
+  if (g.zeta == Z && g.kb == K) {                                                        \
+    hipLaunchKernelGGL((k_adjcount<Z, K>), grid, blk, lds, s, g, disp, b.p_cnt);         \
+    return;                                                                              \
+  }
+  LFSR_CNT(2, 3) LFSR_CNT(2, 5) LFSR_CNT(2, 7) LFSR_CNT(2, 9) LFSR_CNT(3, 5) LFSR_CNT(3, 7) LFSR_CNT(3, 9)
+  LFSR_CNT(4, 7) LFSR_CNT(4, 9)
+#undef LFSR_CNT
+}
 
 void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b, int gate) {
   hipLaunchKernelGGL(k_merge, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, (const float*)b.adj, out,
