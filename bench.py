@@ -86,7 +86,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iters", type=int, default=0, help="override the ADMM iteration count (profiling only)")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP16/BF16 storage runs")
-    ap.add_argument("--serve-jobs", type=int, default=200, help="jobs in the serving stream (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=0,
+                    help="jobs in a serving stream run in a child process (0: skip; see DESIGN.md)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="serving arrival rate, jobs/s")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -120,7 +121,8 @@ def main():
     breakdown = None
     for i in range(max(args.warmup, 1)):
         if i == 0:
-            solver.lfsr_profile_begin(capacity=launches_per_solve * 6 + 64)
+            # every launch of a solve: per iteration 8 + 7 K kernels at most
+            solver.lfsr_profile_begin(capacity=N * (8 + 7 * K) + 64)
         solver.lfsr_solve(y, disp, out=out, stats=False)
         if i == 0:
             breakdown = solver.lfsr_profile_end()
@@ -216,18 +218,19 @@ def main():
         line["precision"] = prec
 
     if args.serve_jobs > 0:
-        from paper_2206_05047_amd import serve
+        # in a child process: a failure there must not lose the line above
+        import subprocess
 
-        wl = serve.Workload()
-        times, kinds = serve.stream(args.serve_jobs, args.serve_rate)
-        pool = serve.run_pool(wl, times, kinds, arena_bytes=40 << 30, max_slots=32)
-        log(f"[bench] serving pool: {pool}")
-        fifo = serve.run_fifo(wl, times, kinds)
-        log(f"[bench] serving one-at-a-time: {fifo}")
-        line["serving"] = {"workload": f"{args.serve_jobs} seeded jobs, Poisson arrivals at {args.serve_rate:g} jobs/s, "
-                                       "types uniform over 3x3/5x5/9x9 views x (x2 256^2, x2 512^2, x3 768^2, "
-                                       "x3 1152^2) x f32/f16 storage",
-                           "pool": pool, "one_at_a_time": fifo}
+        res = subprocess.run([sys.executable, "-m", "paper_2206_05047_amd.serve", str(args.serve_jobs),
+                              str(args.serve_rate)], cwd=ROOT, capture_output=True, text=True, timeout=600)
+        serving = None
+        for ln in res.stdout.splitlines():
+            if ln.startswith("{"):
+                serving = json.loads(ln)
+        if res.returncode != 0 or serving is None:
+            serving = {"error": f"serving run exited with status {res.returncode}"}
+        log(f"[bench] serving: {serving}")
+        line["serving"] = serving
 
     if not args.no_cpu_baseline:
         import oracle

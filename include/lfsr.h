@@ -204,7 +204,7 @@ typedef enum {
   LFSR_K_NLTV = 2,    /* NLTV z/w-step and divergence */
   LFSR_K_NORMAL = 3,  /* normal-operator assembly G^T G p and <p, Hp> */
   LFSR_K_CG = 4,      /* CG start / update kernels */
-  LFSR_K_OTHER = 5,   /* edge weight, iteration bookkeeping */
+  LFSR_K_OTHER = 5,   /* edge weight, merge of the adjoint's partial images, iteration bookkeeping */
   LFSR_K_COUNT = 6
 } lfsr_kernel_kind;
 

@@ -285,18 +285,15 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   // z/w-steps of both blocks; e and the NLTV divergence feed v
   timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_wzd(g, h->disp, h->y, s, b); });
   if (g.sd > 0) timed(h, LFSR_K_NLTV, s, [&] { launch_tv(g, s, b); });
-  timed(h, LFSR_K_ADJOINT, s, [&] {
-    launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm, forward_blocks(g));
-    launch_merge(g, b.r, s, b, kGateAdmm);
-  });
+  timed(h, LFSR_K_ADJOINT, s, [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm, forward_blocks(g)); });
+  timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.r, s, b, kGateAdmm); });
   timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b); });
   // x-step: K CG steps on G^T G delta = -v, accumulated straight into the FP32 estimate
   for (int k = 1; k <= h->prm.cg_iters; ++k) {
     timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_cg(g, b.pv, h->disp, s, b, kGateAdmm | kGateCg); });
-    timed(h, LFSR_K_ADJOINT, s, [&] {
-      launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g));
-      launch_merge(g, b.hp, s, b, kGateAdmm | kGateCg);
-    });
+    timed(h, LFSR_K_ADJOINT, s,
+          [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g)); });
+    timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.hp, s, b, kGateAdmm | kGateCg); });
     timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgupd(g, k, s, b); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });

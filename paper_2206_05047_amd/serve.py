@@ -157,3 +157,27 @@ def run_fifo(wl: Workload, times, kinds):
     for s in solvers.values():
         s.close()
     return _summary(lat, work, t_end)
+
+
+def main(argv):
+    """python -m paper_2206_05047_amd.serve JOBS RATE: one JSON line with the
+    pool's and the one-at-a-time server's latency summaries."""
+    import json
+    import sys
+
+    n = int(argv[0]) if argv else 200
+    rate = float(argv[1]) if len(argv) > 1 else 20.0
+    wl = Workload()
+    times, kinds = stream(n, rate)
+    pool = run_pool(wl, times, kinds, arena_bytes=40 << 30, max_slots=32)
+    print(f"pool {pool}", file=sys.stderr, flush=True)
+    fifo = run_fifo(wl, times, kinds)
+    print(json.dumps({"workload": f"{n} seeded jobs, Poisson arrivals at {rate:g} jobs/s, types uniform over "
+                                  "3x3/5x5/9x9 views x (x2 256^2, x2 512^2, x3 768^2, x3 1152^2) x f32/f16 storage",
+                      "pool": pool, "one_at_a_time": fifo}), flush=True)
+
+
+if __name__ == "__main__":
+    import sys
+
+    main(sys.argv[1:])
