@@ -345,41 +345,34 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
 // lattice columns from a wave-private LDS row buffer.  ZETA, KB and TLY are
 // compile-time so that the position walk and the tap selection unroll.
 // grid = (ceil(sx/f_tlx), ceil(sy/TLY), ceil(sk/f_vpb)).
-// The position walk of k_fwdcol for NV views at once: warp every blur
-// position of the lane's column and accumulate the vertical blur at the TLY
-// lattice rows.  (NV = 1 in use: two interleaved views need more registers
-// than the walk can hold without spilling.)
-template <int NV, int NY, int TLY, int ZETA, int KB>
+// The position walk of k_fwdcol: warp every blur position of the lane's
+// column and accumulate the vertical blur at the TLY lattice rows.  The tile
+// pitch is the compile-time kColPitch: a tap address is one float FMA (exact
+// on these small integers) and one conversion away from the warp's floors,
+// and the four taps are two paired LDS reads at immediate offsets.
+template <int NY, int TLY, int ZETA, int KB>
 __device__ __forceinline__ void fwd_walk(const Geom& g, const float* __restrict__ xs, const float (&om)[NY],
-                                         int cbase, int SX, const float (&tau)[NV], const float (&rho)[NV],
-                                         float (&acc)[NV][TLY]) {
+                                         int cbase, float tau, float rho, float (&acc)[TLY]) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int i = 0; i < TLY; ++i) acc[v][i] = 0.f;
+  for (int i = 0; i < TLY; ++i) acc[i] = 0.f;
+  const float* xc = xs + cbase;
 #pragma unroll
   for (int py = 0; py < NY; ++py) {
-    float val[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const float sy = tau[v] * om[py], sx = rho[v] * om[py];
-      const float fy0 = floorf(sy), fx0 = floorf(sx);
-      const float fy = sy - fy0, fx = sx - fx0;
-      // |row| < 2^23: the 24-bit multiply is exact
-      const int off = cbase + __mul24(py + (int)fy0, SX) + (int)fx0;
-      const float a = xs[off], b = xs[off + 1], c = xs[off + SX], d = xs[off + SX + 1];
-      const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
-      val[v] = fmaf(fy, bot - top, top);
-    }
+    const float sy = tau * om[py], sx = rho * om[py];
+    const float fy0 = floorf(sy), fx0 = floorf(sx);
+    const float fy = sy - fy0, fx = sx - fx0;
+    // tile cell of tap (0, 0), relative to (row 0, lane column): exact in float
+    const int rel = (int)fmaf(fy0 + (float)py, (float)kColPitch, fx0);
+    const float* q = xc + rel;
+    const float a = q[0], b = q[1], c = q[kColPitch], d = q[kColPitch + 1];
+    const float top = fmaf(fx, b - a, a), bot = fmaf(fx, d - c, c);
+    const float val = fmaf(fy, bot - top, top);
     // the lattice rows i this position reaches: 0 <= py - i ZETA < KB
 #pragma unroll
     for (int j = 0; j < (KB + ZETA - 1) / ZETA; ++j) {
       const int i = py / ZETA - j;
       const int t = py - i * ZETA;  // compile-time after unrolling
-      if (i >= 0 && i < TLY && t < KB) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v][i] = fmaf(g.g[t], val[v], acc[v][i]);
-      }
+      if (i >= 0 && i < TLY && t < KB) acc[i] = fmaf(g.g[t], val, acc[i]);
     }
   }
 }
@@ -397,13 +390,13 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __rest
   extern __shared__ float smem[];
   const int h = g.halo, tlx = g.f_tlx;
   const int NX = (tlx - 1) * ZETA + KB;
-  const int SY = NY + 2 * h, SX = NX + 2 * h;
+  const int SY = NY + 2 * h, SX = NX + 2 * h;  // SX <= kColPitch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float* xs = smem;                                  // [SY][SX] source tile, zero outside the image
-  float* vb = smem + SY * SX + wave * (TLY * NX);    // wave-private [TLY][NX] vertical-blur rows
+  float* xs = smem;                                      // [SY][kColPitch] source tile, zero outside the image
+  float* vb = smem + SY * kColPitch + wave * (TLY * NX);  // wave-private [TLY][NX] vertical-blur rows
   const int i0 = blockIdx.y * TLY, j0 = blockIdx.x * tlx;
   const int Yp0 = i0 * ZETA - RB, Xp0 = j0 * ZETA - RB;
-  stage_tile(xs, SX, src, g.H, g.W, Yp0 - h, Xp0 - h, SY, SX);
+  stage_tile(xs, kColPitch, src, g.H, g.W, Yp0 - h, Xp0 - h, SY, SX);
 
   // this lane's column of blur positions: clamped disparity, 0 outside the
   // image (the zero tile then makes the sample vanish, as B's zero padding
@@ -419,7 +412,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __rest
     om[py] = disp[in ? (size_t)Y * g.W + X : 0];
     om[py] = in ? fminf(fmaxf(om[py], -g.disp_bound), g.disp_bound) : 0.f;
   }
-  const int cbase = h * SX + px + h;  // tile offset of (row 0, this column)
+  const int cbase = h * kColPitch + px + h;  // tile offset of (row 0, this column)
   // outputs of this lane: lattice point (oi, oj) of the tile, slot s
   const float invT = 1.f / (float)tlx;
   int orow[NO], ocol[NO];
@@ -491,11 +484,10 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __rest
     const int ka = k / g.V, kc = k - ka * g.V;
     float yv[NO], w0[NO];
     load_wzd(k, yv, w0);
-    const float tau[1] = {(float)(ka - (g.U - 1) / 2)};
-    const float rho[1] = {(float)(kc - (g.V - 1) / 2)};
-    float acc[1][TLY];
-    fwd_walk<1, NY, TLY, ZETA, KB>(g, xs, om, cbase, SX, tau, rho, acc);
-    finish(acc[0], k, yv, w0);
+    const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
+    float acc[TLY];
+    fwd_walk<NY, TLY, ZETA, KB>(g, xs, om, cbase, tau, rho, acc);
+    finish(acc, k, yv, w0);
   }
   const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   {
@@ -779,11 +771,11 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   constexpr int ESL = (RL * LX + 63) / 64;
   constexpr int MM = (2 * RB) / ZETA + 1;            // taps per polyphase phase (at most)
   extern __shared__ float smem[];
-  const int h = g.halo, EY = g.a_ey, EX = g.a_ex;  // EY = TH + 2h, EX = TW + 2h
-  unsigned* acc = reinterpret_cast<unsigned*>(smem);
+  const int h = g.halo, EY = g.a_ey, EX = g.a_ex;  // EY = TH + 2h, EX = TW + 2h <= kColPitch
+  unsigned* acc = reinterpret_cast<unsigned*>(smem);  // [EY][kColPitch]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float* e_ = smem + EY * EX + wave * (RL * LX);  // wave-private LR rows
-  for (int i = tid; i < EY * EX; i += kThreads) acc[i] = 0u;
+  float* e_ = smem + EY * kColPitch + wave * (RL * LX);  // wave-private LR rows
+  for (int i = tid; i < EY * kColPitch; i += kThreads) acc[i] = 0u;
 
   // fixed-point scale from the producer's block maxima (order-free, so exact)
   float mloc = 0.f;
@@ -861,7 +853,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   }
   __syncthreads();  // accumulator zeroed
 
-  const int cb0 = h * EX + x + h;  // accumulator cell of (row 0, this column)
+  unsigned* const accl = acc + (h * kColPitch + x + h);  // accumulator cell of (row 0, this column)
   for (; k < k1; k += 4) {
 #pragma unroll
     for (int s = 0; s < ESL; ++s)
@@ -906,9 +898,12 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
       const float wy1 = __builtin_amdgcn_fractf(sy), wx1 = __builtin_amdgcn_fractf(sx);
       const float u1 = u * wy1, u0 = u - u1;
       const float br = u1 * wx1, bl = u1 - br, tr = u0 * wx1, tl = u0 - tr;
-      // W_k^T: the four cells W_k read (two row bases, +1 column as an immediate offset)
-      unsigned* c0 = acc + (__mul24(floor_i(sy), EX) + floor_i(sx)) + (cb0 + r * EX);
-      unsigned* c1 = c0 + EX;
+      // W_k^T: the four cells W_k read (the row, the second tap row and the
+      // +1 column are immediate offsets: the pitch is compile-time)
+      int cell = floor_i(sy) * kColPitch + floor_i(sx);
+      asm("" : "+v"(cell));  // keeps the cell index whole: one shift-add to the lane's byte address
+      unsigned* c0 = accl + cell + r * kColPitch;
+      unsigned* c1 = c0 + kColPitch;
       atomicAdd(c0, (unsigned)round_i(tl));
       atomicAdd(c0 + 1, (unsigned)round_i(tr));
       atomicAdd(c1, (unsigned)round_i(bl));
@@ -918,7 +913,8 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   __syncthreads();
   const size_t tiles = (size_t)g.a_nty * g.a_ntx;
   float* o = outp + ((size_t)blockIdx.z * tiles + (size_t)blockIdx.y * g.a_ntx + blockIdx.x) * (size_t)(EY * EX);
-  for (int idx = tid; idx < EY * EX; idx += kThreads) o[idx] = (float)(int)acc[idx] * invS;
+  for (int rr = wave; rr < EY; rr += 4)
+    for (int c = lane; c < EX; c += 64) o[rr * EX + c] = (float)(int)acc[rr * kColPitch + c] * invS;
 }
 
 // Contribution counts of k_adjcol: the same tiles, view groups and targets,
@@ -1533,7 +1529,7 @@ static inline void fwd_dims(const Geom& g, int& NY, int& NX, int& SY, int& SX) {
 size_t forward_lds(const Geom& g) {
   int NY, NX, SY, SX;
   fwd_dims(g, NY, NX, SY, SX);
-  if (g.f_col) return sizeof(float) * ((size_t)SY * SX + 4 * (size_t)g.f_tly * NX);
+  if (g.f_col) return sizeof(float) * ((size_t)SY * kColPitch + 4 * (size_t)g.f_tly * NX);
   return sizeof(float) * ((size_t)SY * SX + (size_t)NY * NX + (size_t)NY * g.f_tlx);
 }
 
@@ -1554,7 +1550,9 @@ bool forward_col_setup(Geom& g) {
   // the widest tile with the fewest tile columns
   const int ncol = (g.sx + tmax - 1) / tmax;
   t.f_tlx = (g.sx + ncol - 1) / ncol;
-  if (forward_lds(t) > 60 * 1024) return false;
+  int NY, NX, SY, SX;
+  fwd_dims(t, NY, NX, SY, SX);
+  if (SX > kColPitch || forward_lds(t) > 60 * 1024) return false;
   g = t;
   return true;
 }
@@ -1578,7 +1576,7 @@ size_t adjoint_lds(const Geom& g) {
   if (g.a_col) {
     const int z = g.zeta, CF = g.rb / z;
     const int RL = (g.a_th - 1 + g.rb) / z + CF + 1, LXc = (g.a_tw - 1 + g.rb) / z + CF + 1;
-    return 4 * (size_t)g.a_ey * g.a_ex + sizeof(float) * 4 * (size_t)RL * LXc;
+    return 4 * (size_t)g.a_ey * kColPitch + sizeof(float) * 4 * (size_t)RL * LXc;
   }
   int ci, LY, LX, MM, PAD;
   adj_dims(g, ci, LY, LX, MM, PAD);
@@ -1618,6 +1616,7 @@ bool adjoint_col_setup(Geom& g) {
   t.a_tlx = t.a_tw / g.zeta;
   t.a_ey = t.a_th + 2 * g.halo;
   t.a_ex = t.a_tw + 2 * g.halo;
+  if (t.a_ex > kColPitch) return false;
   const size_t lds = adjoint_lds(t);
   if (lds > 64 * 1024) return false;
   t.a_nty = (g.H + t.a_th - 1) / t.a_th;
