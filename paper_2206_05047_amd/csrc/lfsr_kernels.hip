@@ -1191,6 +1191,117 @@ __global__ __launch_bounds__(kThreads) void k_hp(Geom g, const float* __restrict
   if (tid == 0) part[blockIdx.x + gridDim.x * blockIdx.y] = v[0];
 }
 
+// k_hp with a compile-time window radius: lane = tile column, wave w = a
+// strip of kTvTileY/4 consecutive rows.  p and m^2 are staged interleaved,
+// so each window row a strip needs is 2 RW + 1 paired 8-byte LDS reads shared
+// by the strip's pixels, and every term of the Laplacian is plain VALU work
+// (same terms and weights as tv_laplacian, summed by window row).
+template <bool INTERIOR, int RW>
+__device__ __forceinline__ void hp_strip(const Geom& g, const float2* __restrict__ pm, int lx, int r0, int Y0, int X,
+                                         float (&pz)[kTvTileY / 4], float (&lap)[kTvTileY / 4]) {
+  constexpr int HS = kTvTileY / 4, WN = 2 * RW + 1, LXd = kTvTileX + 2 * RW, CTR = (WN * WN - 1) / 2;
+  float mz[HS];
+  // boundary tiles: bit j of rok = window row j inside the image, bit q of
+  // cok = column offset q - RW inside (interior tiles skip the test)
+  unsigned rok = 0u, cok = 0u;
+  if (!INTERIOR) {
+#pragma unroll
+    for (int j = 0; j < HS + 2 * RW; ++j) {
+      const int Yn = Y0 + r0 + j - RW;
+      rok |= (Yn >= 0 && Yn < g.H) ? 1u << j : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < WN; ++q) {
+      const int Xn = X + q - RW;
+      cok |= (Xn >= 0 && Xn < g.W) ? 1u << q : 0u;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    const float2 c = pm[(r0 + i + RW) * LXd + lx + RW];
+    pz[i] = c.x;
+    mz[i] = c.y;
+    lap[i] = 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < HS + 2 * RW; ++j) {  // window row j: tile row r0 + j - RW
+    float2 n[WN];
+#pragma unroll
+    for (int q = 0; q < WN; ++q) n[q] = pm[(r0 + j) * LXd + lx + q];
+#pragma unroll
+    for (int i = 0; i < HS; ++i) {
+      const int dy = j - RW - i;
+      if (dy < -RW || dy > RW) continue;
+#pragma unroll
+      for (int q = 0; q < WN; ++q) {
+        const int dx = q - RW;
+        if (dy == 0 && dx == 0) continue;
+        const int idx = (dy + RW) * WN + (dx + RW);
+        const int d = idx < CTR ? idx : idx - 1;
+        float t = g.cd2[d] * (mz[i] + n[q].y) * (pz[i] - n[q].x);
+        if (!INTERIOR) t = ((rok >> j) & (cok >> q) & 1u) ? t : 0.f;
+        lap[i] += t;
+      }
+    }
+  }
+}
+
+template <int RW>
+__global__ __launch_bounds__(kThreads, 6) void k_hpstrip(Geom g, const float* __restrict__ pv,
+                                                      const float* __restrict__ m, float* hp,
+                                                      double* __restrict__ part,
+                                                      const DevScalars* __restrict__ sc, int gate, int with_dot) {
+  static_assert(RW > 0, "compile-time radius");
+  if (gated(sc, g, gate)) return;
+  constexpr int HS = kTvTileY / 4, LXd = kTvTileX + 2 * RW, LYd = kTvTileY + 2 * RW;
+  extern __shared__ float2 smem_f2[];
+  float2* pm = smem_f2;  // [LYd][LXd] (p, m^2), zero outside the image
+  const int X0 = blockIdx.x * kTvTileX, Y0 = blockIdx.y * kTvTileY;
+  const int tid = threadIdx.x;
+  {
+    constexpr int n = LYd * LXd, BATCH = 4;
+    for (int base = tid; base < n; base += kThreads * BATCH) {
+      float pvv[BATCH], mv[BATCH];
+      int off[BATCH];
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) {
+        const int e = base + j * kThreads;
+        const int r = e / LXd, c = e - r * LXd;
+        const int Y = Y0 - RW + r, X = X0 - RW + c;
+        const bool ok = e < n && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
+        const size_t o = ok ? (size_t)Y * g.W + X : 0;
+        pvv[j] = ok ? pv[o] : 0.f;
+        mv[j] = ok ? m[o] : 0.f;
+        off[j] = e < n ? e : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j)
+        if (off[j] >= 0) pm[off[j]] = make_float2(pvv[j], mv[j] * mv[j]);
+    }
+  }
+  __syncthreads();
+  const bool interior = X0 - RW >= 0 && X0 + kTvTileX + RW <= g.W && Y0 - RW >= 0 && Y0 + kTvTileY + RW <= g.H;
+  const int lx = tid & 63, r0 = (tid >> 6) * HS;
+  const int X = X0 + lx;
+  float pz[HS], lap[HS];
+  if (interior) hp_strip<true, RW>(g, pm, lx, r0, Y0, X, pz, lap);
+  else hp_strip<false, RW>(g, pm, lx, r0, Y0, X, pz, lap);
+  double s_dot = 0.0;
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    const int Y = Y0 + r0 + i;
+    if (Y >= g.H || X >= g.W) continue;
+    const size_t o = (size_t)Y * g.W + X;
+    const float v = g.cA * hp[o] + g.half_theta * lap[i];
+    hp[o] = v;
+    if (with_dot) s_dot += (double)pz[i] * (double)v;
+  }
+  if (!with_dot) return;
+  double v[1] = {s_dot};
+  block_sum<1>(v);
+  if (tid == 0) part[blockIdx.x + gridDim.x * blockIdx.y] = v[0];
+}
+
 // ---------------------------------------------------------------------------
 // CG start (Algorithm 2 from delta = 0): v = A^T e + (vartheta/2) S^T f,
 // r = -v, p = r, partials of <r, r>.  Block 0 also closes the wz-step's
@@ -1793,14 +1904,14 @@ void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
 
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot) {
-#define LFSR_HP(R)                                                                                              \
-  hipLaunchKernelGGL(k_hp<R>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php, \
+#define LFSR_HP(K, R)                                                                                     \
+  hipLaunchKernelGGL(K<R>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php, \
                      (const DevScalars*)b.sc, gate, with_dot)
   switch (g.rw) {
-    case 1: LFSR_HP(1); break;
-    case 2: LFSR_HP(2); break;
-    case 3: LFSR_HP(3); break;
-    default: LFSR_HP(0); break;
+    case 1: LFSR_HP(k_hpstrip, 1); break;
+    case 2: LFSR_HP(k_hpstrip, 2); break;
+    case 3: LFSR_HP(k_hpstrip, 3); break;
+    default: LFSR_HP(k_hp, 0); break;
   }
 #undef LFSR_HP
 }
