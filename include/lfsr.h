@@ -83,7 +83,7 @@ typedef enum { LFSR_F32 = 0, LFSR_F16 = 1, LFSR_BF16 = 2 } lfsr_storage;
 typedef struct {
   int32_t ang_rows, ang_cols; /* U, V: angular grid, both odd (centre view = reference) */
   int32_t lr_h, lr_w;         /* s_y, s_x: LR view size */
-  int32_t scale;              /* zeta >= 1: HR = scale * LR (sec 4.1) */
+  int32_t scale;              /* zeta in 1..8: HR = scale * LR (sec 4.1); HR at most 32768 per side and 2^28 pixels */
   int32_t n_disp;             /* 1: one disparity map on the reference view (the only form supported) */
   int32_t blur_size;          /* odd, 1..31; <= 0 with blur_sigma <= 0: paper default (see below) */
   float blur_sigma;           /* Gaussian std-dev in HR px; <= 0: sqrt(scale^2-1)/4 (sec 4.1), size 2*ceil(3 sigma)+1 */

@@ -108,6 +108,9 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   if (p->scale < 1 || p->scale > 8) return fail(err, "scale must be in 1..8");
   if ((long long)p->lr_h * p->scale > 32768 || (long long)p->lr_w * p->scale > 32768)
     return fail(err, "HR size above 32768 per side");
+  // one HR plane stays below 1 GiB of floats (32-bit byte offsets in the kernels)
+  if ((long long)p->lr_h * p->scale * (long long)p->lr_w * p->scale > (1LL << 28))
+    return fail(err, "HR image above 2^28 pixels");
   if (p->n_disp != 1) return fail(err, "n_disp must be 1 (one disparity map on the reference view)");
   if (!(std::isfinite(p->lambda1) && std::isfinite(p->lambda2)) || p->lambda1 < 0.f || p->lambda2 < 0.f ||
       p->lambda1 + p->lambda2 <= 0.f)

@@ -88,6 +88,20 @@ __device__ __forceinline__ void sum_parts(const double* __restrict__ part, int n
   block_sum<N>(out);
 }
 
+// Tile of a block in a 1-D grid of 8 * ceil(ntx * nty / 8) blocks.  Blocks
+// are dispatched to the eight XCDs round-robin, so XCD k (blocks k, k+8, ...)
+// gets the contiguous row-major run of tiles k * ceil(n/8) ..: neighbouring
+// tiles, which read each other's halo cache lines, then share one L2.  The
+// padding blocks (t >= ntx * nty) return false.
+__device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty, int& t) {
+  const int nb = ntx * nty, per = (nb + 7) / 8, b = blockIdx.x;
+  t = (b & 7) * per + (b >> 3);
+  if (t >= nb) return false;
+  ty = t / ntx;
+  tx = t - ty * ntx;
+  return true;
+}
+
 __device__ __forceinline__ bool gated(const DevScalars* sc, const Geom& g, int gate) {
   if ((gate & kGateAdmm) && sc->admm_done) return true;
   if ((gate & kGateCg) && sc->cg_done) return true;
@@ -98,6 +112,30 @@ __device__ __forceinline__ bool gated(const DevScalars* sc, const Geom& g, int g
 __device__ __forceinline__ double* stats_row(const Geom& g, double* stats, const DevScalars* sc) {
   const int r = sc->iters_done < g.n_iter ? sc->iters_done : g.n_iter - 1;
   return stats + (size_t)r * 6;
+}
+
+// Raw buffer access to one plane of a storage-typed array: a scalar
+// descriptor per plane and a 32-bit byte offset per lane (no 64-bit address
+// per access).  Descriptor word 3 is the gfx9-family raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  } else {
+    const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+    return (float)__builtin_bit_cast(T, b);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off, T v) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
+  }
 }
 
 // Stage a rows x cols tile, element (r, c) = src[(Y0 + r) * W + X0 + c] (zero
@@ -1033,37 +1071,29 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     sl[rr] = (ly + rw) * LXd + (lx + rw);
   }
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  // software pipeline: the dual values of offsets d+1 and d+2 are in flight while d is used
-  float c0[4], c2[4], n0[4], n2[4];
+  // byte offset of pixel (Y[rr], X) within one dual plane (a plane is below
+  // 2 GiB), so every dual access is a uniform plane pointer plus this offset
+  unsigned boff[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) boff[rr] = in[rr] ? (unsigned)(((size_t)Y[rr] * g.W + X) * sizeof(T)) : 0u;
   auto load = [&](int d, float (&w0)[4], float (&w2)[4]) __attribute__((always_inline)) {
     const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const T* wd = wo + (size_t)d * g.p;
+    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(wd);
+    const __amdgpu_buffer_rsrc_t r2 = plane_rsrc(wd - ((ptrdiff_t)dy * g.W + dx));  // plane shifted by -d
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      const size_t o = (size_t)Y[rr] * g.W + X;
-      w0[rr] = in[rr] ? (float)wd[o] : 0.f;
+      w0[rr] = in[rr] ? buf_load<T>(r0, boff[rr]) : 0.f;
       const bool bin = INTERIOR || (in[rr] && Y[rr] - dy >= 0 && Y[rr] - dy < g.H && X - dx >= 0 && X - dx < g.W);
-      w2[rr] = bin ? (float)wd[o - (ptrdiff_t)dy * g.W - dx] : 0.f;
+      w2[rr] = bin ? buf_load<T>(r2, boff[rr]) : 0.f;
     }
   };
-  if (SD > 0) load(0, c0, c2);
-  if (SD > 1) load(1, n0, n2);
-  // kept rolled: unrolling lets the compiler hoist every dual load and spill
-#pragma unroll 1
-  for (int d = 0; d < SD; ++d) {
-    float w0[4], w2[4];
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      w0[rr] = c0[rr];
-      w2[rr] = c2[rr];
-      c0[rr] = n0[rr];
-      c2[rr] = n2[rr];
-    }
-    if (d + 2 < SD) load(d + 2, n0, n2);
+  // offset d with its dual values w0 = w_d(z), w2 = w_d(z - d)
+  auto step = [&](int d, const float (&w0)[4], const float (&w2)[4]) __attribute__((always_inline)) {
     const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const int dd = dy * LXd + dx;
     const float c = g.cd[d];
-    T* wnd = wn_ + (size_t)d * g.p;
+    const __amdgpu_buffer_rsrc_t rn = plane_rsrc(wn_ + (size_t)d * g.p);
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       if (!in[rr]) continue;
@@ -1071,7 +1101,7 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
       const bool fin = INTERIOR || (Y[rr] + dy >= 0 && Y[rr] + dy < g.H && X + dx >= 0 && X + dx < g.W);
       const float gv = fin ? c * mz * (xz - xs[sl[rr] + dd]) : 0.f;
       const float wn = clipf(gv + w0[rr], g.clip);
-      wnd[(size_t)Y[rr] * g.W + X] = (T)wn;
+      buf_store<T>(rn, boff[rr], (T)wn);
       if (fin) acc[rr] = fmaf(c * mz, 2.f * wn - w0[rr], acc[rr]);
       const double dw = (double)wn - (double)w0[rr];
       s_abs += fabs((double)gv);
@@ -1083,6 +1113,44 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
         const float wn2 = clipf(g2 + w2[rr], g.clip);
         acc[rr] = fmaf(-(c * mm), 2.f * wn2 - w2[rr], acc[rr]);
       }
+    }
+  };
+  if constexpr (RW > 0) {
+    // ring of P in-flight offsets: slot j holds offset d0 + j and is refilled
+    // with offset d0 + j + P right after its use, so no register is moved and
+    // P - 1 offsets of loads stay in flight behind the one being used
+    constexpr int P = 4, SDc = (2 * RW + 1) * (2 * RW + 1) - 1;
+    static_assert(SDc % P == 0, "the window's offset count is a multiple of 4");
+    float b0[P][4], b2[P][4];
+#pragma unroll
+    for (int j = 0; j < P; ++j) load(j, b0[j], b2[j]);
+#pragma unroll 1
+    for (int d0 = 0; d0 < SDc - P; d0 += P) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        step(d0 + j, b0[j], b2[j]);
+        load(d0 + j + P, b0[j], b2[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) step(SDc - P + j, b0[j], b2[j]);
+  } else {
+    // software pipeline: the dual values of offsets d+1 and d+2 are in flight while d is used
+    float c0[4], c2[4], n0[4], n2[4];
+    if (SD > 0) load(0, c0, c2);
+    if (SD > 1) load(1, n0, n2);
+#pragma unroll 1
+    for (int d = 0; d < SD; ++d) {
+      float w0[4], w2[4];
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        w0[rr] = c0[rr];
+        w2[rr] = c2[rr];
+        c0[rr] = n0[rr];
+        c2[rr] = n2[rr];
+      }
+      if (d + 2 < SD) load(d + 2, n0, n2);
+      step(d, w0, w2);
     }
   }
 #pragma unroll
@@ -1097,12 +1165,14 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x
                                                  T* ws0, T* ws1, float* __restrict__ vs,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
+  int tx, ty, tt;
+  if (!xcd_tile((g.W + kTvTileX - 1) / kTvTileX, (g.H + kTvTileY - 1) / kTvTileY, tx, ty, tt)) return;
   extern __shared__ float smem[];
   const int rw = RW > 0 ? RW : g.rw;
   const int LXd = kTvTileX + 2 * rw, LYd = kTvTileY + 2 * rw;
   float* xs = smem;
   float* ms = xs + LYd * LXd;
-  const int X0 = blockIdx.x * kTvTileX, Y0 = blockIdx.y * kTvTileY;
+  const int X0 = tx * kTvTileX, Y0 = ty * kTvTileY;
   stage_tile(xs, LXd, x, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
   stage_tile(ms, LXd, m, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
   __syncthreads();
@@ -1115,9 +1185,8 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x
   double v[2] = {s_abs, s_dw};
   block_sum<2>(v);
   if (threadIdx.x == 0) {
-    const unsigned bid = blockIdx.x + gridDim.x * blockIdx.y;
-    part[(size_t)bid * 2 + 0] = v[0];
-    part[(size_t)bid * 2 + 1] = v[1];
+    part[(size_t)tt * 2 + 0] = v[0];
+    part[(size_t)tt * 2 + 1] = v[1];
   }
 }
 
@@ -1890,7 +1959,7 @@ void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
   by_storage(b.st, [&](auto* tag) {
     using T = LFSR_ELEM(tag);
 #define LFSR_TV(R)                                                                                                 \
-  hipLaunchKernelGGL((k_tv<T, R>), tv_grid(g), dim3(kThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m, \
+  hipLaunchKernelGGL((k_tv<T, R>), dim3(8 * ((nblocks(tv_grid(g)) + 7) / 8)), dim3(kThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m, \
                      (T*)b.wS[0], (T*)b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc)
     switch (g.rw) {
       case 1: LFSR_TV(1); break;
