@@ -1024,12 +1024,57 @@ __global__ __launch_bounds__(kThreads) void k_absmax(const float* __restrict__ v
 
 // out = sum of the adjoint partial images (dense A^T e, read by the CG
 // kernels and returned by the operator entry point).
+// Same sum when the halo is at most half a tile: a pixel then lies in the
+// halo of at most one neighbouring tile row and one neighbouring tile column,
+// so each view group contributes at most four values.  All four are loaded
+// unconditionally (absent ones from the pixel's own cell, a cache hit) and
+// masked afterwards, so the loads of every group are in flight together.
+__device__ __forceinline__ float adj_merge_near(const Geom& g, const float* __restrict__ adj, int Y, int X) {
+  const int ty = (int)(((float)Y + 0.5f) * g.a_inv_th), tx = (int)(((float)X + 0.5f) * g.a_inv_tw);
+  const int ly = Y - ty * g.a_th, lx = X - tx * g.a_tw, h = g.halo;
+  const int sy = ly < h ? -1 : (ly >= g.a_th - h ? 1 : 0);
+  const int sx = lx < h ? -1 : (lx >= g.a_tw - h ? 1 : 0);
+  const bool hy = sy != 0 && ty + sy >= 0 && ty + sy < g.a_nty;
+  const bool hx = sx != 0 && tx + sx >= 0 && tx + sx < g.a_ntx;
+  const bool hxy = hx && hy;
+  const long long tile = (long long)g.a_ey * g.a_ex;
+  const long long grp = (long long)g.a_nty * g.a_ntx * tile;
+  const long long r0 = (long long)(ly + h) * g.a_ex, r1 = (long long)(ly - sy * g.a_th + h) * g.a_ex;
+  const int c0 = lx + h, c1 = lx - sx * g.a_tw + h;
+  const long long t00 = ((long long)ty * g.a_ntx + tx) * tile;
+  const long long o00 = t00 + r0 + c0;
+  const long long o01 = hx ? ((long long)ty * g.a_ntx + tx + sx) * tile + r0 + c1 : o00;
+  const long long o10 = hy ? ((long long)(ty + sy) * g.a_ntx + tx) * tile + r1 + c0 : o00;
+  const long long o11 = hxy ? ((long long)(ty + sy) * g.a_ntx + tx + sx) * tile + r1 + c1 : o00;
+  float v[8][4];
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    if (z >= g.a_vg) break;
+    const float* a = adj + z * grp;
+    v[z][0] = a[o00];
+    v[z][1] = a[o01];
+    v[z][2] = a[o10];
+    v[z][3] = a[o11];
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    if (z >= g.a_vg) break;
+    s += v[z][0];
+    s += hx ? v[z][1] : 0.f;
+    s += hy ? v[z][2] : 0.f;
+    s += hxy ? v[z][3] : 0.f;
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restrict__ adj, float* __restrict__ out,
                                                     const DevScalars* __restrict__ sc, int gate) {
   if (gated(sc, g, gate)) return;
+  const bool near = 2 * g.halo <= g.a_th && 2 * g.halo <= g.a_tw && g.a_vg <= 8;
   for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
     const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
-    out[o] = adj_merge(g, adj, Y, X);
+    out[o] = near ? adj_merge_near(g, adj, Y, X) : adj_merge(g, adj, Y, X);
   }
 }
 
