@@ -48,17 +48,19 @@ bool choose_tiles(Geom& g, std::string* err) {
   if (vpb > g.sk) vpb = g.sk;
   g.f_vpb = (int)vpb;
   if (forward_col_setup(g)) {
-    // four waves per block, each a view at a time.  Views are split into
-    // groups so that a launch is about 1.5 rounds of resident blocks (4 per CU
-    // on 256 CUs): long view loops amortise the tile staging, and the partial
-    // second round keeps the tail short.
+    // NW waves per block (8 for quad cells, 4 for the plain tile), each a view
+    // at a time.  Views are split into groups so that a launch is about 1.5
+    // rounds of resident blocks (2 or 4 per CU on 256 CUs): long view loops
+    // amortise the tile staging, and the partial second round keeps the tail
+    // short.
+    const long long nw = g.f_col == 2 ? 8 : 4, slots = g.f_col == 2 ? 512 : 1024;
     const long long ct = (long long)((g.sy + g.f_tly - 1) / g.f_tly) * ((g.sx + g.f_tlx - 1) / g.f_tlx);
-    long long groups = (1536 + ct / 2) / ct;
-    const long long gmax = (g.sk + 3) / 4;
+    long long groups = (3 * slots / 2 + ct / 2) / ct;
+    const long long gmax = (g.sk + nw - 1) / nw;
     if (groups < 1) groups = 1;
     if (groups > gmax) groups = gmax;
-    const long long vpw = (g.sk + 4 * groups - 1) / (4 * groups);
-    g.f_vpb = (int)(4 * vpw);
+    const long long vpw = (g.sk + nw * groups - 1) / (nw * groups);
+    g.f_vpb = (int)(nw * vpw);
   }
 
   // adjoint: prefer >= 1024 tiles; the HR tile must be at least the halo

@@ -49,8 +49,9 @@ struct Geom {
   float cg_tol;
   float stop_tol;
   int n_iter;                 // rows of the statistics history
-  // forward-operator tiling: LR tile and views per block.  f_col = 1 selects
-  // the column-per-lane kernel (then f_vpb = 4 waves x views per wave).
+  // forward-operator tiling: LR tile and views per block.  f_col selects the
+  // column-per-lane kernel: 1 = plain tile, 4 waves; 2 = quad-cell tile, 8
+  // waves (f_vpb = waves x views per wave).
   int f_tly, f_tlx, f_vpb;
   int f_col;
   // adjoint tiling: LR tile, HR tile, extended (haloed) tile, tile grid

@@ -58,10 +58,11 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Sum N doubles over the block; every thread receives the totals.
-template <int N>
+// Sum N doubles over a block of NW waves (fixed order); every thread
+// receives the totals.
+template <int N, int NW = 4>
 __device__ __forceinline__ void block_sum(double (&v)[N]) {
-  __shared__ double sh[4 * N];
+  __shared__ double sh[NW * N];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int n = 0; n < N; ++n) v[n] = wave_sum(v[n]);
@@ -72,7 +73,12 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
   }
   __syncthreads();
 #pragma unroll
-  for (int n = 0; n < N; ++n) v[n] = ((sh[n] + sh[N + n]) + sh[2 * N + n]) + sh[3 * N + n];
+  for (int n = 0; n < N; ++n) {
+    double t = sh[n];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) t += sh[w * N + n];
+    v[n] = t;
+  }
 }
 
 // Fixed-order sum of component c of nb per-block partials (stride N); every
@@ -415,8 +421,37 @@ __device__ __forceinline__ void fwd_walk(const Geom& g, const float* __restrict_
   }
 }
 
-template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO>
-__global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
+// The position walk over quad cells: cell (r, c) of the staged tile holds
+// (v, v[c+1] - v, v[r+1] - v, v[r+1][c+1] - v[r+1] - v[c+1] + v), so the
+// bilinear sample at fraction (fy, fx) is v + fx dh + fy (dv + fx dhv): three
+// FMAs after one 16-byte LDS read.
+template <int NY, int TLY, int ZETA, int KB>
+__device__ __forceinline__ void fwd_walk_q(const Geom& g, const float4* __restrict__ qs, const float (&om)[NY],
+                                           int cbase, float sxf, float tau, float rho, float (&acc)[TLY]) {
+#pragma unroll
+  for (int i = 0; i < TLY; ++i) acc[i] = 0.f;
+  const float4* qc = qs + cbase;
+#pragma unroll
+  for (int py = 0; py < NY; ++py) {
+    const float sy = tau * om[py], sx = rho * om[py];
+    const float fy0 = floorf(sy), fx0 = floorf(sx);
+    const float fy = sy - fy0, fx = sx - fx0;
+    const int rel = (int)fmaf(fy0 + (float)py, sxf, fx0);  // exact: small integers
+    const float4 c = qc[rel];
+    const float val = fmaf(fy, fmaf(fx, c.w, c.z), fmaf(fx, c.y, c.x));
+#pragma unroll
+    for (int j = 0; j < (KB + ZETA - 1) / ZETA; ++j) {
+      const int i = py / ZETA - j;
+      const int t = py - i * ZETA;
+      if (i >= 0 && i < TLY && t < KB) acc[i] = fmaf(g.g[t], val, acc[i]);
+    }
+  }
+}
+
+// QUAD: eight waves per block share a tile of quad cells (fwd_walk_q);
+// otherwise four waves share a plain tile at pitch kColPitch.
+template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO, bool QUAD>
+__global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads, QUAD ? 2 : 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
                                                      const float* __restrict__ disp, TO* __restrict__ out,
                                                      const float* __restrict__ y, TO* __restrict__ wD,
                                                      double* __restrict__ part, float* __restrict__ pmax,
@@ -425,16 +460,51 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __rest
   constexpr int RB = KB / 2;
   constexpr int NY = (TLY - 1) * ZETA + KB;
   constexpr int NO = (TLY * ((64 - KB) / ZETA + 1) + 63) / 64;  // outputs per lane and view
-  extern __shared__ float smem[];
+  constexpr int NW = QUAD ? 8 : 4;                                // waves per block
+  extern __shared__ float4 smem_q[];
+  float* smem = reinterpret_cast<float*>(smem_q);
   const int h = g.halo, tlx = g.f_tlx;
   const int NX = (tlx - 1) * ZETA + KB;
-  const int SY = NY + 2 * h, SX = NX + 2 * h;  // SX <= kColPitch
+  const int SY = NY + 2 * h, SX = NX + 2 * h;  // plain tile: SX <= kColPitch
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  float* xs = smem;                                      // [SY][kColPitch] source tile, zero outside the image
-  float* vb = smem + SY * kColPitch + wave * (TLY * NX);  // wave-private [TLY][NX] vertical-blur rows
+  const int TW4 = QUAD ? 4 * SY * SX : SY * kColPitch;  // floats of the source tile
+  float* xs = smem;                                      // plain: [SY][kColPitch], zero outside the image
+  const float4* qs = smem_q;                             // quad: [SY][SX] cells
+  float* vb = smem + TW4 + wave * (TLY * NX);            // wave-private [TLY][NX] vertical-blur rows
   const int i0 = blockIdx.y * TLY, j0 = blockIdx.x * tlx;
   const int Yp0 = i0 * ZETA - RB, Xp0 = j0 * ZETA - RB;
-  stage_tile(xs, kColPitch, src, g.H, g.W, Yp0 - h, Xp0 - h, SY, SX);
+  if constexpr (QUAD) {
+    // cells from the source (zero outside the image); each cell reads its
+    // 2 x 2 neighbourhood, so the tile's last row and column hold cells no
+    // sample reaches (the walk's taps stay within rows/columns <= SY-2, SX-2)
+    const int n = SY * SX;
+    const float inv = 1.f / (float)SX;
+    for (int base = tid; base < n; base += NW * 64 * 2) {
+      float v[2][4];
+      int off[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int e = base + j * NW * 64;
+        const int r = (int)(((float)e + 0.5f) * inv), c = e - r * SX;
+        const int Y = Yp0 - h + r, X = Xp0 - h + c;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int Yq = Y + (q >> 1), Xq = X + (q & 1);
+          const bool ok = e < n && Yq >= 0 && Yq < g.H && Xq >= 0 && Xq < g.W;
+          const float t = (float)src[ok ? (size_t)Yq * g.W + Xq : 0];
+          v[j][q] = ok ? t : 0.f;
+        }
+        off[j] = e < n ? e : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        if (off[j] >= 0)
+          smem_q[off[j]] = make_float4(v[j][0], v[j][1] - v[j][0], v[j][2] - v[j][0],
+                                       (v[j][3] - v[j][2]) - (v[j][1] - v[j][0]));
+    }
+  } else {
+    stage_tile(xs, kColPitch, src, g.H, g.W, Yp0 - h, Xp0 - h, SY, SX);
+  }
 
   // this lane's column of blur positions: clamped disparity, 0 outside the
   // image (the zero tile then makes the sample vanish, as B's zero padding
@@ -450,7 +520,7 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __rest
     om[py] = disp[in ? (size_t)Y * g.W + X : 0];
     om[py] = in ? fminf(fmaxf(om[py], -g.disp_bound), g.disp_bound) : 0.f;
   }
-  const int cbase = h * kColPitch + px + h;  // tile offset of (row 0, this column)
+  const int cbase = h * (QUAD ? SX : kColPitch) + px + h;  // tile cell of (row 0, this column)
   // outputs of this lane: lattice point (oi, oj) of the tile, slot s
   const float invT = 1.f / (float)tlx;
   int orow[NO], ocol[NO];
@@ -518,27 +588,33 @@ __global__ __launch_bounds__(kThreads, 4) void k_fwdcol(Geom g, const TS* __rest
       }
     }
   };
-  for (int k = k0 + wave; k < k1; k += 4) {
+  for (int k = k0 + wave; k < k1; k += NW) {
     const int ka = k / g.V, kc = k - ka * g.V;
     float yv[NO], w0[NO];
     load_wzd(k, yv, w0);
     const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
     float acc[TLY];
-    fwd_walk<NY, TLY, ZETA, KB>(g, xs, om, cbase, tau, rho, acc);
+    if constexpr (QUAD) fwd_walk_q<NY, TLY, ZETA, KB>(g, qs, om, cbase, (float)SX, tau, rho, acc);
+    else fwd_walk<NY, TLY, ZETA, KB>(g, xs, om, cbase, tau, rho, acc);
     finish(acc, k, yv, w0);
   }
   const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off, 64));
-    __shared__ float sm[4];
+    __shared__ float sm[NW];
     if (lane == 0) sm[wave] = vmax;
     __syncthreads();
-    if (tid == 0) pmax[bid] = fmaxf(fmaxf(sm[0], sm[1]), fmaxf(sm[2], sm[3]));
+    if (tid == 0) {
+      float m = sm[0];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) m = fmaxf(m, sm[w]);
+      pmax[bid] = m;
+    }
   }
   if constexpr (WZD) {
     double v[3] = {s_abs, s_sq, s_dw};
-    block_sum<3>(v);
+    block_sum<3, NW>(v);
     if (tid == 0) {
       part[(size_t)bid * 3 + 0] = v[0];
       part[(size_t)bid * 3 + 1] = v[1];
@@ -1754,6 +1830,7 @@ static inline void fwd_dims(const Geom& g, int& NY, int& NX, int& SY, int& SX) {
 size_t forward_lds(const Geom& g) {
   int NY, NX, SY, SX;
   fwd_dims(g, NY, NX, SY, SX);
+  if (g.f_col == 2) return sizeof(float) * (4 * (size_t)SY * SX + 8 * (size_t)g.f_tly * NX);
   if (g.f_col) return sizeof(float) * ((size_t)SY * kColPitch + 4 * (size_t)g.f_tly * NX);
   return sizeof(float) * ((size_t)SY * SX + (size_t)NY * NX + (size_t)NY * g.f_tlx);
 }
@@ -1777,6 +1854,13 @@ bool forward_col_setup(Geom& g) {
   t.f_tlx = (g.sx + ncol - 1) / ncol;
   int NY, NX, SY, SX;
   fwd_dims(t, NY, NX, SY, SX);
+  // quad cells when two 8-wave blocks fit a CU's LDS, else the plain tile
+  Geom q = t;
+  q.f_col = 2;
+  if (forward_lds(q) <= 80 * 1024) {
+    g = q;
+    return true;
+  }
   if (SX > kColPitch || forward_lds(t) > 60 * 1024) return false;
   g = t;
   return true;
@@ -1891,12 +1975,16 @@ static void launch_fwd_kb(const Geom& g, const TS* src, const float* disp, TO* o
   const dim3 grid = forward_grid(g), blk(kThreads);
   const size_t lds = forward_lds(g);
   if (g.f_col) {
-#define LFSR_FWC(Z, K)                                                                                             \
-  if (g.zeta == Z && g.kb == K) {                                                                                  \
-    constexpr int TL = fwdcol_tly(Z, K);                                                                           \
-    hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO>), grid, blk, lds, s, g, src, disp, out, y, wD, part, pmax, \
-                       sc, gate);                                                                                  \
-    return;                                                                                                        \
+#define LFSR_FWC(Z, K)                                                                                            \
+  if (g.zeta == Z && g.kb == K) {                                                                                 \
+    constexpr int TL = fwdcol_tly(Z, K);                                                                          \
+    if (g.f_col == 2)                                                                                             \
+      hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, true>), grid, dim3(2 * kThreads), lds, s, g, src, disp, \
+                         out, y, wD, part, pmax, sc, gate);                                                       \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, false>), grid, blk, lds, s, g, src, disp, out, y, wD,   \
+                         part, pmax, sc, gate);                                                                   \
+    return;                                                                                                       \
   }
     LFSR_FWC(2, 3) LFSR_FWC(2, 5) LFSR_FWC(2, 7) LFSR_FWC(2, 9) LFSR_FWC(3, 5) LFSR_FWC(3, 7) LFSR_FWC(3, 9)
     LFSR_FWC(4, 7) LFSR_FWC(4, 9)

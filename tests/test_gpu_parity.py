@@ -76,6 +76,32 @@ def test_normal_operator_matches_oracle(lfsr, case):
     assert rel_err(got, ref) < OP_TOL
 
 
+# 9 x 9 views at scale 3 with |disparity| up to 3: the warp halo is 13 pixels,
+# too wide for the quad-cell forward tile (16 (30 + 26)(54 + 26) bytes of cells
+# + 13824 of row buffers > 80 KiB), so this case runs the plain column tile.
+WIDE = dict(synth.CONFIGS["c1"], name="wide", U=9, V=9, sy=32, sx=32, zeta=3, kb=9, sigma_b=1.5, win=7,
+            n_iter=2, seed=13, scene="layers", n_layers=4, disp_max=3.0)
+
+
+@pytest.fixture(scope="module")
+def wide():
+    print("[case wide]", flush=True)
+    return make_case(WIDE)
+
+
+def test_operators_wide_halo(lfsr, wide):
+    s = _solver(lfsr, wide["cfg"])
+    o = wide["oracle"]
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 1, o.hr_shape).astype(np.float32)
+    assert rel_err(_n(s.lfsr_forward(_t(x), _t(wide["disp"]))), o.forward(x, wide["disp"])) < OP_TOL
+    e = rng.standard_normal(o.lr_shape).astype(np.float32)
+    assert rel_err(_n(s.lfsr_adjoint(_t(e), _t(wide["disp"]))), o.adjoint(e, wide["disp"])) < OP_TOL
+    m = rng.uniform(0.2, 1.0, o.hr_shape).astype(np.float32)
+    got = _n(s.lfsr_normal(_t(x), _t(wide["disp"]), _t(m)))
+    assert rel_err(got, o.normal_apply(wide["disp"], m, x)) < OP_TOL
+
+
 def test_edge_weight_and_bicubic_match_oracle(lfsr, case):
     s = _solver(lfsr, case["cfg"])
     o = case["oracle"]
