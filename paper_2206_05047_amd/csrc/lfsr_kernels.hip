@@ -855,11 +855,12 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
 // k0 + wave, k0 + wave + 4, ... of the block's view group.  Fixed point: a
 // count pass (k_adjcount, once per disparity map) records the most
 // contributions n any cell of the block receives; every contribution is at
-// most M = max |lr| in magnitude, so with S = 2^(30 - ceil log2(n + 1) -
-// ceil log2 M) each scaled contribution stays below 2^(30 - hd) and the
-// exact integer sum of a cell below 2^30: the int32 wrap-around of
+// most M = max |lr| in magnitude, so with hd = ceil log2(n + 1) and
+// S = 2^(31 - hd - ceil log2 M) each scaled contribution, rounded to
+// nearest (no bias), is at most 2^(31 - hd) and the exact integer sum of a
+// cell at most (2^hd - 1) 2^(31 - hd) < 2^31: the int32 wrap-around of
 // intermediate sums cancels, and integer addition keeps the result bitwise
-// reproducible.  Contributions are rounded to nearest (no bias).  Lane x owns tile column x and walks the tile rows: B^T D^T is a
+// reproducible.  Lane x owns tile column x and walks the tile rows: B^T D^T is a
 // horizontal polyphase pass per staged LR row (three LDS reads) followed by a
 // vertical pass in registers with compile-time taps, so a pixel costs a
 // fraction of an LDS read instead of several; then W_k^T sends u to the four
@@ -904,7 +905,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   if (M > 0.f) (void)frexpf(M, &eM);  // M < 2^eM
   const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   (void)frexpf((float)pcnt[bid] + 1.f, &hd);  // n + 1 <= 2^hd
-  const int sexp = min(max(30 - hd - eM, -120), 120);
+  const int sexp = min(max(31 - hd - eM, -120), 120);
   const float S = ldexpf(1.f, sexp), invS = ldexpf(1.f, -sexp);
 
   const int Y0 = blockIdx.y * TH, X0 = blockIdx.x * TW;  // tile origin (multiples of ZETA)
