@@ -449,9 +449,15 @@ __device__ __forceinline__ void fwd_walk_q(const Geom& g, const float4* __restri
 }
 
 // QUAD: eight waves per block share a tile of quad cells (fwd_walk_q);
-// otherwise four waves share a plain tile at pitch kColPitch.
+// otherwise four waves share a plain tile at pitch kColPitch.  The second
+// launch bound is a minimum of waves per SIMD: 4 caps VGPRs at 128 (two
+// quad blocks or four plain blocks per CU).  The FP32 quad kernels fit 128
+// without the cap (one shape reaches 134 and keeps three waves per SIMD) and
+// schedule better without it: with it the wz-step spills in its view loop.
+// The 16-bit variants need the cap to stay at 128.
 template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO, bool QUAD>
-__global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads, QUAD ? 2 : 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
+__global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
+                             (QUAD && sizeof(TS) == 4 && sizeof(TO) == 4) ? 2 : 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
                                                      const float* __restrict__ disp, TO* __restrict__ out,
                                                      const float* __restrict__ y, TO* __restrict__ wD,
                                                      double* __restrict__ part, float* __restrict__ pmax,
