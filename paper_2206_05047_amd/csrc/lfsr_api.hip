@@ -294,12 +294,13 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.r, s, b, kGateAdmm); });
   timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b); });
   // x-step: K CG steps on G^T G delta = -v, accumulated straight into the FP32 estimate
+  const int fuse = merge_fusable(g) ? 1 : 0;  // the normal assembly gathers A^T A p itself
   for (int k = 1; k <= h->prm.cg_iters; ++k) {
     timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_cg(g, b.pv, h->disp, s, b, kGateAdmm | kGateCg); });
     timed(h, LFSR_K_ADJOINT, s,
           [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm | kGateCg, forward_blocks(g)); });
-    timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.hp, s, b, kGateAdmm | kGateCg); });
-    timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1); });
+    if (!fuse) timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.hp, s, b, kGateAdmm | kGateCg); });
+    timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1, fuse); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgupd(g, k, s, b); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });
   }
@@ -547,8 +548,9 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   launch_forward_cg(g, d_p, d_disp, s, h->b, 0);
   launch_adjcount(g, d_disp, s, h->b);
   launch_adjoint(g, h->b.lr, h->b.st, d_disp, s, h->b, 0, forward_blocks(g));
-  launch_merge(g, d_out, s, h->b, 0);
-  launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0);
+  const int fuse = merge_fusable(g) ? 1 : 0;
+  if (!fuse) launch_merge(g, d_out, s, h->b, 0);
+  launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0, fuse);
   return check_hip(h, "lfsr_normal");
 }
 

@@ -150,9 +150,12 @@ int forward_blocks(const Geom& g);
 // dense A^T e from the adjoint's partial images
 void launch_merge(const Geom& g, float* out, hipStream_t s, const Bufs& b, int gate);
 void launch_tv(const Geom& g, hipStream_t s, const Bufs& b);
-// out: merged A^T A pv on entry, H pv on exit
+// out: H pv on exit; on entry the merged A^T A pv, unless fused (then the
+// kernel gathers it from the adjoint's partial images b.adj; only when
+// merge_fusable(g))
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
-               int with_dot);
+               int with_dot, int fused);
+bool merge_fusable(const Geom& g);
 void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b);
 void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b);
 void launch_cgp(const Geom& g, int step, hipStream_t s, const Bufs& b);

@@ -1446,8 +1446,10 @@ __device__ __forceinline__ void hp_strip(const Geom& g, const float2* __restrict
 template <int RW>
 __global__ __launch_bounds__(kThreads, 6) void k_hpstrip(Geom g, const float* __restrict__ pv,
                                                       const float* __restrict__ m, float* hp,
+                                                      const float* __restrict__ adj,
                                                       double* __restrict__ part,
-                                                      const DevScalars* __restrict__ sc, int gate, int with_dot) {
+                                                      const DevScalars* __restrict__ sc, int gate, int with_dot,
+                                                      int fused) {
   static_assert(RW > 0, "compile-time radius");
   if (gated(sc, g, gate)) return;
   constexpr int HS = kTvTileY / 4, LXd = kTvTileX + 2 * RW, LYd = kTvTileY + 2 * RW;
@@ -1489,7 +1491,9 @@ __global__ __launch_bounds__(kThreads, 6) void k_hpstrip(Geom g, const float* __
     const int Y = Y0 + r0 + i;
     if (Y >= g.H || X >= g.W) continue;
     const size_t o = (size_t)Y * g.W + X;
-    const float v = g.cA * hp[o] + g.half_theta * lap[i];
+    // fused: A^T A p gathered here from the adjoint's partial images
+    const float ata = fused ? adj_merge_near(g, adj, Y, X) : hp[o];
+    const float v = g.cA * ata + g.half_theta * lap[i];
     hp[o] = v;
     if (with_dot) s_dot += (double)pz[i] * (double)v;
   }
@@ -2111,18 +2115,25 @@ void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
   });
 }
 
+bool merge_fusable(const Geom& g) {
+  return g.a_col && g.rw >= 1 && g.rw <= 3 && 2 * g.halo <= g.a_th && 2 * g.halo <= g.a_tw && g.a_vg <= 8;
+}
+
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
-               int with_dot) {
-#define LFSR_HP(K, R)                                                                                     \
-  hipLaunchKernelGGL(K<R>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php, \
-                     (const DevScalars*)b.sc, gate, with_dot)
+               int with_dot, int fused) {
+#define LFSR_HPS(R)                                                                                        \
+  hipLaunchKernelGGL(k_hpstrip<R>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, (const float*)b.adj, \
+                     b.p_php, (const DevScalars*)b.sc, gate, with_dot, fused)
   switch (g.rw) {
-    case 1: LFSR_HP(k_hpstrip, 1); break;
-    case 2: LFSR_HP(k_hpstrip, 2); break;
-    case 3: LFSR_HP(k_hpstrip, 3); break;
-    default: LFSR_HP(k_hp, 0); break;
+    case 1: LFSR_HPS(1); break;
+    case 2: LFSR_HPS(2); break;
+    case 3: LFSR_HPS(3); break;
+    default:
+      hipLaunchKernelGGL(k_hp<0>, tv_grid(g), dim3(kThreads), tv_lds(g), s, g, pv, m, out, b.p_php,
+                         (const DevScalars*)b.sc, gate, with_dot);
+      break;
   }
-#undef LFSR_HP
+#undef LFSR_HPS
 }
 
 void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b) {
