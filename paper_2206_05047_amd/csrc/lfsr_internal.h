@@ -24,7 +24,7 @@ constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles (4 
 // LDS row pitch (floats) of the column-per-lane kernels' source tile and
 // accumulator: tile width + 2 halo must fit (halo <= 32)
 constexpr int kColPitch = 128;
-constexpr int kRedBlocks = 1024;  // max grid of the element-wise CG kernels (= partials per reduction)
+constexpr int kRedBlocks = 512;   // max grid of the element-wise CG kernels (= partials per reduction)
 
 // Problem geometry and model constants, passed by value to every kernel.
 struct Geom {
