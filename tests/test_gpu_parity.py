@@ -76,17 +76,20 @@ def test_normal_operator_matches_oracle(lfsr, case):
     assert rel_err(got, ref) < OP_TOL
 
 
-# 9 x 9 views at scale 3 with |disparity| up to 3: the warp halo is 13 pixels,
-# too wide for the quad-cell forward tile (16 (30 + 26)(54 + 26) bytes of cells
-# + 13824 of row buffers > 80 KiB), so this case runs the plain column tile.
+# 9 x 9 views at scale 3 with a wide warp halo.  disp_bound 3: halo 13, too
+# wide for the quad-cell forward tile (16 (30 + 26)(54 + 26) bytes of cells +
+# 13824 of row buffers > 80 KiB), so the plain column forward tile runs.
+# disp_bound 4.5: halo 19, more than half the adjoint's 33-row tile, so the
+# adjoint's partial images take the general merge and the normal assembly
+# does not gather them itself.
 WIDE = dict(synth.CONFIGS["c1"], name="wide", U=9, V=9, sy=32, sx=32, zeta=3, kb=9, sigma_b=1.5, win=7,
             n_iter=2, seed=13, scene="layers", n_layers=4, disp_max=3.0)
 
 
-@pytest.fixture(scope="module")
-def wide():
-    print("[case wide]", flush=True)
-    return make_case(WIDE)
+@pytest.fixture(scope="module", params=[3.0, 4.5])
+def wide(request):
+    print(f"[case wide disp_max={request.param}]", flush=True)
+    return make_case(dict(WIDE, disp_max=request.param))
 
 
 def test_operators_wide_halo(lfsr, wide):
