@@ -291,10 +291,11 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_wzd(g, h->disp, h->y, s, b); });
   if (g.sd > 0) timed(h, LFSR_K_NLTV, s, [&] { launch_tv(g, s, b); });
   timed(h, LFSR_K_ADJOINT, s, [&] { launch_adjoint(g, b.lr, b.st, h->disp, s, b, kGateAdmm, forward_blocks(g)); });
-  timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.r, s, b, kGateAdmm); });
-  timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b); });
+  // the CG start and the normal assembly gather the adjoint's partial images themselves when they can
+  const int fuse = merge_fusable(g) ? 1 : 0;
+  if (!fuse) timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.r, s, b, kGateAdmm); });
+  timed(h, LFSR_K_CG, s, [&] { launch_cginit(g, s, b, fuse); });
   // x-step: K CG steps on G^T G delta = -v, accumulated straight into the FP32 estimate
-  const int fuse = merge_fusable(g) ? 1 : 0;  // the normal assembly gathers A^T A p itself
   for (int k = 1; k <= h->prm.cg_iters; ++k) {
     timed(h, LFSR_K_FORWARD, s, [&] { launch_forward_cg(g, b.pv, h->disp, s, b, kGateAdmm | kGateCg); });
     timed(h, LFSR_K_ADJOINT, s,
@@ -302,7 +303,8 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
     if (!fuse) timed(h, LFSR_K_OTHER, s, [&] { launch_merge(g, b.hp, s, b, kGateAdmm | kGateCg); });
     timed(h, LFSR_K_NORMAL, s, [&] { launch_hp(g, b.pv, b.m, b.hp, s, b, kGateAdmm | kGateCg, 1, fuse); });
     timed(h, LFSR_K_CG, s, [&] { launch_cgupd(g, k, s, b); });
-    timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });
+    // the direction after the last step is never read (the next x-step starts from p = r)
+    if (k < h->prm.cg_iters) timed(h, LFSR_K_CG, s, [&] { launch_cgp(g, k, s, b); });
   }
   if (b.st != kStF32) timed(h, LFSR_K_CG, s, [&] { launch_fold(g, s, b); });
   timed(h, LFSR_K_OTHER, s, [&] { launch_iter_end(g, s, b); });

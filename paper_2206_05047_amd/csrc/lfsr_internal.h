@@ -156,7 +156,9 @@ void launch_tv(const Geom& g, hipStream_t s, const Bufs& b);
 void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipStream_t s, const Bufs& b, int gate,
                int with_dot, int fused);
 bool merge_fusable(const Geom& g);
-void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b);
+// r holds the merged A^T e on entry, unless fused (then gathered from b.adj;
+// only when merge_fusable(g))
+void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b, int fused);
 void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b);
 void launch_cgp(const Geom& g, int step, hipStream_t s, const Bufs& b);
 void launch_iter_end(const Geom& g, hipStream_t s, const Bufs& b);

@@ -1512,7 +1512,8 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
                                                      float* __restrict__ pv, double* __restrict__ prr,
                                                      const double* __restrict__ pwzd, int nwzd,
                                                      const double* __restrict__ ptv, int ntv,
-                                                     double* __restrict__ stats, DevScalars* __restrict__ sc) {
+                                                     double* __restrict__ stats, DevScalars* __restrict__ sc,
+                                                     const float* __restrict__ adj, int fused) {
   if (sc->admm_done) return;
   double s = 0.0;
   const long long gstride = (long long)gridDim.x * kThreads * 4;
@@ -1523,7 +1524,12 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
       const long long o = o0 + j * kThreads;
       v[j] = 0.f;
       if (o < g.p) {
-        v[j] = r[o];
+        if (fused) {  // A^T e gathered here from the adjoint's partial images
+          const unsigned Y = (unsigned)o / (unsigned)g.W, X = (unsigned)o - Y * (unsigned)g.W;
+          v[j] = adj_merge_near(g, adj, (int)Y, (int)X);
+        } else {
+          v[j] = r[o];
+        }
         if (g.sd > 0) v[j] += g.half_theta * vs[o];
       }
     }
@@ -2136,10 +2142,10 @@ void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipSt
 #undef LFSR_HPS
 }
 
-void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b) {
+void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b, int fused) {
   hipLaunchKernelGGL(k_cginit, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.vs, b.r, b.pv,
                      b.p_rr[0], (const double*)b.p_wzd, nblocks(forward_grid(g)),
-                     (const double*)b.p_tv, nblocks(tv_grid(g)), b.stats, b.sc);
+                     (const double*)b.p_tv, nblocks(tv_grid(g)), b.stats, b.sc, (const float*)b.adj, fused);
 }
 
 void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b) {
