@@ -1286,6 +1286,98 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     if (in[rr]) vs[(size_t)Y[rr] * g.W + X] = acc[rr];
 }
 
+// Interior tiles with 16-bit duals and an even image width: the same
+// per-pixel arithmetic as tv_tile<true>, with the lanes mapped to pixel pairs
+// so that every dual access is a dword (2-byte accesses cost as much per
+// instruction as 4-byte ones here).  Lane l of wave w owns columns
+// 2 (l & 31) and 2 (l & 31) + 1 of rows 2 w + (l >> 5) and that + 8; slot rr
+// = 2 row-step + column.  Pair (X, X + 1), X even, is one aligned dword of a
+// plane; the pulled term's pair (X - dx, X + 1 - dx) is one aligned dword for
+// even dx and the high / low halves of the two dwords around it for odd dx.
+template <typename T, int RW>
+__device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restrict__ xs, const float* __restrict__ ms,
+                                             const T* wo, T* wn_, float* __restrict__ vs, int X0, int Y0,
+                                             double& s_abs, double& s_dw) {
+  static_assert(sizeof(T) == 2 && RW > 0, "16-bit duals, compile-time radius");
+  constexpr int LXd = kTvTileX + 2 * RW, SD = (2 * RW + 1) * (2 * RW + 1) - 1, P = 4;
+  static_assert(SD % P == 0, "the window's offset count is a multiple of 4");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int Y[4], X[4], sl[4];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int lx = 2 * (lane & 31) + (rr & 1), ly = 2 * wave + (lane >> 5) + 8 * (rr >> 1);
+    Y[rr] = Y0 + ly;
+    X[rr] = X0 + lx;
+    sl[rr] = (ly + RW) * LXd + (lx + RW);
+  }
+  unsigned boff[2];  // byte offset of each row's pair (dword aligned)
+#pragma unroll
+  for (int q = 0; q < 2; ++q) boff[q] = (unsigned)(((size_t)Y[2 * q] * g.W + X[2 * q]) * 2);
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  auto half = [](unsigned dw, int hi) __attribute__((always_inline)) {
+    return (float)__builtin_bit_cast(T, (unsigned short)(hi ? dw >> 16 : dw & 0xffffu));
+  };
+  // raw dwords of offset d: a0[q] = pair at z, b0[q] / b1[q] = the dword(s) of the pair at z - d
+  auto load = [&](int d, unsigned (&a0)[2], unsigned (&b0)[2], unsigned (&b1)[2]) __attribute__((always_inline)) {
+    const int dy = win_dy(RW, d), dx = win_dx(RW, d);
+    const T* wd = wo + (size_t)d * g.p;
+    const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(wd);
+    const __amdgpu_buffer_rsrc_t r2 = plane_rsrc(wd - ((ptrdiff_t)dy * g.W + dx));  // plane shifted by -d
+    const unsigned od = (unsigned)(dx & 1) * 2u;  // odd dx: the dwords either side (even: the same one twice)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      a0[q] = __builtin_amdgcn_raw_buffer_load_b32(r0, (int)boff[q], 0, 0);
+      b0[q] = __builtin_amdgcn_raw_buffer_load_b32(r2, (int)(boff[q] - od), 0, 0);
+      b1[q] = __builtin_amdgcn_raw_buffer_load_b32(r2, (int)(boff[q] + od), 0, 0);
+    }
+  };
+  auto step = [&](int d, const unsigned (&a0)[2], const unsigned (&b0)[2], const unsigned (&b1)[2])
+                  __attribute__((always_inline)) {
+    const int dy = win_dy(RW, d), dx = win_dx(RW, d);
+    const int dd = dy * LXd + dx;
+    const float c = g.cd[d];
+    const __amdgpu_buffer_rsrc_t rn = plane_rsrc(wn_ + (size_t)d * g.p);
+    unsigned bits[4];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int q = rr >> 1, h = rr & 1;
+      const float w0 = half(a0[q], h);
+      // odd dx: the pair straddles two dwords (high half of the first, low half of the second)
+      const float w2 = (dx & 1) ? (h ? half(b1[q], 0) : half(b0[q], 1)) : half(b0[q], h);
+      const float xz = xs[sl[rr]], mz = ms[sl[rr]];
+      const float gv = c * mz * (xz - xs[sl[rr] + dd]);
+      const float wn = clipf(gv + w0, g.clip);
+      bits[rr] = __builtin_bit_cast(unsigned short, (T)wn);
+      acc[rr] = fmaf(c * mz, 2.f * wn - w0, acc[rr]);
+      const double dw = (double)wn - (double)w0;
+      s_abs += fabs((double)gv);
+      s_dw += dw * dw;
+      const float mm = ms[sl[rr] - dd];
+      const float g2 = c * mm * (xs[sl[rr] - dd] - xz);
+      const float wn2 = clipf(g2 + w2, g.clip);
+      acc[rr] = fmaf(-(c * mm), 2.f * wn2 - w2, acc[rr]);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      __builtin_amdgcn_raw_buffer_store_b32(bits[2 * q] | (bits[2 * q + 1] << 16), rn, (int)boff[q], 0, 0);
+  };
+  unsigned a0[P][2], b0[P][2], b1[P][2];
+#pragma unroll
+  for (int j = 0; j < P; ++j) load(j, a0[j], b0[j], b1[j]);
+#pragma unroll 1
+  for (int d0 = 0; d0 < SD - P; d0 += P) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      step(d0 + j, a0[j], b0[j], b1[j]);
+      load(d0 + j + P, a0[j], b0[j], b1[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < P; ++j) step(SD - P + j, a0[j], b0[j], b1[j]);
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) vs[(size_t)Y[rr] * g.W + X[rr]] = acc[rr];
+}
+
 // T: storage type of x and of the dual; the dual recomputed for the pulled
 // term is the same FP32 value the owning thread stores (rounded) for w_S'.
 template <typename T, int RW>
@@ -1308,8 +1400,16 @@ __global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x
   T* wn_ = sc->wcur ? ws0 : ws1;
   const bool interior = X0 - rw >= 0 && X0 + kTvTileX + rw <= g.W && Y0 - rw >= 0 && Y0 + kTvTileY + rw <= g.H;
   double s_abs = 0.0, s_dw = 0.0;
-  if (interior) tv_tile<true, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
-  else tv_tile<false, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  if constexpr (sizeof(T) == 2 && RW > 0) {
+    // (odd dx reads the dword past the halo's last column: keep that column inside the row)
+    if (interior && (g.W & 1) == 0 && X0 + kTvTileX + RW + 1 <= g.W)
+      tv_tile_pair<T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    else if (interior) tv_tile<true, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    else tv_tile<false, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  } else {
+    if (interior) tv_tile<true, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    else tv_tile<false, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+  }
   double v[2] = {s_abs, s_dw};
   block_sum<2>(v);
   if (threadIdx.x == 0) {
