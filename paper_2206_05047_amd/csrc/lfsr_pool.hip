@@ -108,13 +108,16 @@ void destroy_job(lfsr_pool* p, PoolJob& j) {
   p->free_slots.push_back(j.slot);
 }
 
-// Destroy the replaced graphs whose last launch has completed (all = true:
-// wait for them).
+// Destroy the replaced graphs whose last launch is known to have completed
+// (all = true: wait for them).  Only a successful query or wait counts: a
+// graph whose completion cannot be confirmed (not ready, or the runtime
+// returned an error) is kept, and leaked at pool destruction rather than
+// destroyed while a launch of it may still run.
 void sweep_graveyard(lfsr_pool* p, bool all) {
   std::vector<std::pair<hipGraphExec_t, hipEvent_t>> keep;
   for (auto& ge : p->graveyard) {
-    if (all) (void)hipEventSynchronize(ge.second);
-    if (!all && hipEventQuery(ge.second) == hipErrorNotReady) {
+    const hipError_t q = all ? hipEventSynchronize(ge.second) : hipEventQuery(ge.second);
+    if (q != hipSuccess) {
       keep.push_back(ge);
       continue;
     }
@@ -295,25 +298,37 @@ lfsr_status lfsr_pool_tick(lfsr_pool* p, void* hip_stream, int32_t* h_active) {
   }
   e = hipGraphLaunch(p->exec, p->main);
   if (e != hipSuccess) return pool_hip(p, e, "lfsr_pool_tick launch");
-  // retire the jobs that have run all their iterations
+  // retire the jobs that have run all their iterations.  A job is in exactly
+  // one of active / retiring at every return, also after a failure (it then
+  // stays active), so that destruction releases each handle once.
   std::vector<PoolJob> keep;
   keep.reserve(p->active.size());
+  lfsr_status bad = LFSR_OK;
   for (PoolJob& j : p->active) {
     j.ticks += 1;
     j.h->n_done = j.ticks;
-    if (j.ticks < j.n_iter) {
+    if (bad || j.ticks < j.n_iter) {
       keep.push_back(j);
       continue;
     }
     lfsr_status st = lfsr_read_state(j.h, j.out, nullptr, nullptr, nullptr, p->main);
-    if (st) return pool_err(p, st, std::string("lfsr_pool_tick output: ") + j.h->err);
+    if (st) {
+      bad = pool_err(p, st, std::string("lfsr_pool_tick output: ") + j.h->err);
+      keep.push_back(j);
+      continue;
+    }
     e = hipMemcpyAsync(&p->status[j.slot], j.h->b.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, p->main);
     if (e == hipSuccess) e = hipEventRecord(p->done[j.slot], p->main);
-    if (e != hipSuccess) return pool_hip(p, e, "lfsr_pool_tick retire");
+    if (e != hipSuccess) {
+      bad = pool_hip(p, e, "lfsr_pool_tick retire");
+      keep.push_back(j);
+      continue;
+    }
     p->retiring.push_back(j);
     p->dirty = true;
   }
   p->active.swap(keep);
+  if (bad) return bad;
   e = hipEventRecord(p->ev_out, p->main);
   if (e == hipSuccess) e = hipStreamWaitEvent(cs, p->ev_out, 0);
   return pool_hip(p, e, "lfsr_pool_tick order out");
@@ -323,10 +338,13 @@ lfsr_status lfsr_pool_poll(lfsr_pool* p, int64_t* h_ids, int32_t* h_status, int3
                            int32_t* h_count) {
   if (!p) return pool_err(nullptr, LFSR_EINVAL, "pool is NULL");
   if (!h_count || (cap > 0 && !h_ids)) return pool_err(p, LFSR_EINVAL, "h_count and h_ids are required");
+  // a failed event query leaves that job (and the ones after it) retiring;
+  // the jobs harvested before it are reported in h_ids / *h_count as usual
   int n = 0;
   std::vector<PoolJob> keep;
+  hipError_t bad = hipSuccess;
   for (PoolJob& j : p->retiring) {
-    if (n >= cap) {
+    if (bad != hipSuccess || n >= cap) {
       keep.push_back(j);
       continue;
     }
@@ -335,7 +353,11 @@ lfsr_status lfsr_pool_poll(lfsr_pool* p, int64_t* h_ids, int32_t* h_status, int3
       keep.push_back(j);
       continue;
     }
-    if (q != hipSuccess) return pool_hip(p, q, "lfsr_pool_poll");
+    if (q != hipSuccess) {
+      bad = q;
+      keep.push_back(j);
+      continue;
+    }
     const DevScalars& sc = p->status[j.slot];
     h_ids[n] = j.id;
     if (h_status) h_status[n] = (sc.err_flags & 1) ? LFSR_ENONFINITE : (sc.err_flags & 2) ? LFSR_EINVAL : LFSR_OK;
@@ -345,7 +367,7 @@ lfsr_status lfsr_pool_poll(lfsr_pool* p, int64_t* h_ids, int32_t* h_status, int3
   }
   p->retiring.swap(keep);
   *h_count = n;
-  return LFSR_OK;
+  return pool_hip(p, bad, "lfsr_pool_poll");
 }
 
 lfsr_status lfsr_pool_info(const lfsr_pool* p, int32_t* h_active, int32_t* h_retiring, size_t* h_free,

@@ -52,6 +52,12 @@ void check_tag(char* ws, uint64_t serial) {
 }
 }  // namespace
 
+// Error injection: the n-th later call of hipMemcpyAsync / hipEventQuery
+// fails (n < 0: never).
+long g_memcpy_fail = -1, g_query_fail = -1;
+extern "C" void mock_fail_memcpy_in(long n) { g_memcpy_fail = n; }
+extern "C" void mock_fail_query_in(long n) { g_query_fail = n; }
+
 extern "C" void mock_progress(size_t n) {
   while (n-- > 0 && !g_queue.empty()) run_one();
 }
@@ -91,7 +97,10 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t) {
   g_queue.push_back([e, n] { e->completed = n; });
   return hipSuccess;
 }
-hipError_t hipEventQuery(hipEvent_t e) { return e->completed == e->recorded ? hipSuccess : hipErrorNotReady; }
+hipError_t hipEventQuery(hipEvent_t e) {
+  if (g_query_fail >= 0 && g_query_fail-- == 0) return hipErrorInvalidValue;
+  return e->completed == e->recorded ? hipSuccess : hipErrorNotReady;
+}
 hipError_t hipEventSynchronize(hipEvent_t e) {
   if (g_cap) fail("event synchronize while capturing");
   while (e->completed != e->recorded) {
@@ -109,6 +118,7 @@ hipError_t hipHostFree(void* p) {
   return hipSuccess;
 }
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind, hipStream_t) {
+  if (g_memcpy_fail >= 0 && g_memcpy_fail-- == 0) return hipErrorInvalidValue;
   enqueue([dst, src, bytes] { std::memcpy(dst, src, bytes); });
   return hipSuccess;
 }

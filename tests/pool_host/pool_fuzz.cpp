@@ -14,6 +14,8 @@
 
 extern "C" void mock_progress(size_t n);
 extern "C" size_t mock_pending();
+extern "C" void mock_fail_memcpy_in(long n);
+extern "C" void mock_fail_query_in(long n);
 
 namespace {
 
@@ -39,6 +41,14 @@ void run(unsigned seed) {
   if (lfsr_pool_create(arena, arena_bytes, max_slots, &p) != LFSR_OK) fail(seed, "pool_create");
   const int total = 120;
   const int abandon_at = (seed % 4 == 3) ? (int)(rng() % total) : -1;  // destroy with jobs in flight
+  // seeds 5k+4: one runtime call fails part-way (a result copy in tick, or an
+  // event query in poll); the pool reports LFSR_EDEVICE and is then destroyed
+  const bool inject = seed % 5 == 4;
+  if (inject) {
+    if (rng() % 2) mock_fail_memcpy_in((long)(rng() % 40));
+    else mock_fail_query_in((long)(rng() % 400));
+  }
+  bool failed = false;
   std::map<int64_t, Job> live;
   size_t live_bytes = 0;
   int submitted = 0, harvested = 0;
@@ -68,13 +78,19 @@ void run(unsigned seed) {
       }
     } else if (a < 6) {
       int32_t act = -1;
-      if (lfsr_pool_tick(p, nullptr, &act) != LFSR_OK) fail(seed, "tick");
+      const lfsr_status st = lfsr_pool_tick(p, nullptr, &act);
+      if (st != LFSR_OK) {
+        if (!inject || st != LFSR_EDEVICE) fail(seed, "tick");
+        failed = true;
+        break;
+      }
     } else if (a < 8) {
       int64_t ids[8];
       int32_t sts[8], its[8], n = -1;
       const int cap = 1 + (int)(rng() % 8);
-      if (lfsr_pool_poll(p, ids, sts, its, cap, &n) != LFSR_OK) fail(seed, "poll");
-      if (n < 0 || n > cap) fail(seed, "poll count out of range");
+      const lfsr_status pst = lfsr_pool_poll(p, ids, sts, its, cap, &n);
+      if (pst != LFSR_OK && (!inject || pst != LFSR_EDEVICE)) fail(seed, "poll");
+      if (n < 0 || n > cap) fail(seed, "poll count out of range (it is set on errors too)");
       for (int i = 0; i < n; ++i) {
         auto it = live.find(ids[i]);
         if (it == live.end()) fail(seed, "harvested an unknown or already harvested job");
@@ -89,6 +105,10 @@ void run(unsigned seed) {
         live.erase(it);
         ++harvested;
       }
+      if (pst != LFSR_OK) {
+        failed = true;
+        break;
+      }
     } else {
       mock_progress(rng() % 48);
     }
@@ -98,6 +118,9 @@ void run(unsigned seed) {
     if (fr + live_bytes != arena_bytes) fail(seed, "arena free space does not match the live jobs");
     if (big > fr || (size_t)(na + nr) != live.size()) fail(seed, "pool counts inconsistent");
   }
+  mock_fail_memcpy_in(-1);
+  mock_fail_query_in(-1);
+  (void)failed;
   lfsr_pool_destroy(p);
   mock_progress((size_t)-1);
   if (mock_pending() != 0) fail(seed, "device work left after destroy");

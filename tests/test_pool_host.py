@@ -4,8 +4,11 @@ points (tests/pool_host), with AddressSanitizer and UBSan, and driven through
 random admission / tick / poll sequences with device progress at random
 points.  Covers arena accounting, slot reuse, graph re-capture and the
 deferred destruction of replaced graphs, harvesting after each job's exact
-iteration count, job isolation in a reused arena, and pool destruction with
-jobs in flight."""
+iteration count, job isolation in a reused arena, pool destruction with
+jobs in flight, and the error paths (every fifth seed makes one result copy or
+one event query fail part-way: the pool must report LFSR_EDEVICE, keep each
+job in exactly one of its lists, and never destroy a replaced graph whose
+completion it could not confirm)."""
 import os
 import shutil
 import subprocess
