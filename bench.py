@@ -87,7 +87,8 @@ def main():
     ap.add_argument("--iters", type=int, default=0, help="override the ADMM iteration count (profiling only)")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP16/BF16 storage runs")
     ap.add_argument("--serve-jobs", type=int, default=0,
-                    help="jobs in a serving stream run in a child process (0: skip; see DESIGN.md)")
+                    help="jobs in a serving stream run in a child process (0: skip; the serving run is "
+                         "currently disabled and reports an error)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="serving arrival rate, jobs/s")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -165,6 +165,11 @@ def main(argv):
     import json
     import sys
 
+    # Switched off: a run of this stream ended in a host-side segmentation
+    # fault within seconds of its start (the per-type set-up or the first
+    # pool ticks), while the pool's GPU tests and its host-side bookkeeping
+    # tests pass.  It stays off until that fault has a cause.
+    raise SystemExit("serving run disabled: an unresolved host-side segmentation fault in its set-up")
     n = int(argv[0]) if argv else 200
     rate = float(argv[1]) if len(argv) > 1 else 20.0
     wl = Workload()
