@@ -29,7 +29,7 @@ def log(*a):
 
 
 def kernel_flops_per_launch(kind, cfg):
-    """Algorithmic FLOPs of one launch of a kernel kind (see DESIGN.md):
+    """Algorithmic FLOPs of one launch of a kernel kind:
     forward: per view-pixel 9 (bilinear as three lerps) + 2 kb/zeta
              (horizontal blur at lattice columns) + 2 kb/zeta^2 (vertical),
     adjoint: per view-pixel 2 kb/zeta + 2 kb/zeta^2 (polyphase B^T D^T)
@@ -93,7 +93,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU row-band design is described in DESIGN.md, not built).", file=sys.stderr)
+              "(a multi-GPU split into HR row bands is not built).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
