@@ -108,6 +108,21 @@ __device__ __forceinline__ bool xcd_tile(int ntx, int nty, int& tx, int& ty, int
   return true;
 }
 
+// The same XCD-aware order inside a grid of any shape, as a bijection: the
+// block's linear index b (x fastest) runs on XCD b % 8, and XCD k takes the
+// contiguous run of linear tile indices [k q + min(k, r), ... + count) where
+// nb = 8 q + r; the run is decoded back into (x, y, z) of the grid.
+__device__ __forceinline__ void xcd_block3(int& bx, int& by, int& bz) {
+  const unsigned nx = gridDim.x, nxy = gridDim.x * gridDim.y, nb = nxy * gridDim.z;
+  const unsigned b = blockIdx.x + nx * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned q = nb >> 3, r = nb & 7u, k = b & 7u;
+  const unsigned t = k * q + (k < r ? k : r) + (b >> 3);
+  bz = (int)(t / nxy);
+  const unsigned rem = t - (unsigned)bz * nxy;
+  by = (int)(rem / nx);
+  bx = (int)(rem - (unsigned)by * nx);
+}
+
 __device__ __forceinline__ bool gated(const DevScalars* sc, const Geom& g, int gate) {
   if ((gate & kGateAdmm) && sc->admm_done) return true;
   if ((gate & kGateCg) && sc->cg_done) return true;
@@ -477,7 +492,9 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
   float* xs = smem;                                      // plain: [SY][kColPitch], zero outside the image
   const float4* qs = smem_q;                             // quad: [SY][SX] cells
   float* vb = smem + TW4 + wave * (TLY * NX);            // wave-private [TLY][NX] vertical-blur rows
-  const int i0 = blockIdx.y * TLY, j0 = blockIdx.x * tlx;
+  int bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int i0 = by * TLY, j0 = bx * tlx;
   const int Yp0 = i0 * ZETA - RB, Xp0 = j0 * ZETA - RB;
   if constexpr (QUAD) {
     // cells from the source (zero outside the image); each cell reads its
@@ -545,7 +562,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
 
   double s_abs = 0.0, s_sq = 0.0, s_dw = 0.0;
   float vmax = 0.f;
-  const int k0 = blockIdx.z * g.f_vpb;
+  const int k0 = bz * g.f_vpb;
   const int k1 = min(g.sk, k0 + g.f_vpb);
   // horizontal blur at the lattice columns and the epilogue of one view
   auto finish = [&](const float (&acc)[TLY], int k, const float (&yv)[NO], const float (&w0)[NO])
@@ -909,12 +926,14 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   const float M = fmaxf(fmaxf(smax[0], smax[1]), fmaxf(smax[2], smax[3]));
   int eM = 0, hd = 0;
   if (M > 0.f) (void)frexpf(M, &eM);  // M < 2^eM
-  const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  int bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const unsigned bid = bx + gridDim.x * (by + gridDim.y * bz);  // the tile's count-pass block
   (void)frexpf((float)pcnt[bid] + 1.f, &hd);  // n + 1 <= 2^hd
   const int sexp = min(max(31 - hd - eM, -120), 120);
   const float S = ldexpf(1.f, sexp), invS = ldexpf(1.f, -sexp);
 
-  const int Y0 = blockIdx.y * TH, X0 = blockIdx.x * TW;  // tile origin (multiples of ZETA)
+  const int Y0 = by * TH, X0 = bx * TW;  // tile origin (multiples of ZETA)
   const int i0 = Y0 / ZETA - CF, jb = X0 / ZETA - CF;    // first staged LR row / column
   // staged LR values of this lane (offset within a view; -1 = zero)
   int eoff[ESL];
@@ -962,7 +981,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
     om[r] = in ? fminf(fmaxf(om[r], -g.disp_bound), g.disp_bound) : 0.f;
   }
   float ereg[ESL];
-  const int k0 = blockIdx.z * g.a_vpb;
+  const int k0 = bz * g.a_vpb;
   const int k1 = min(g.sk, k0 + g.a_vpb);
   int k = k0 + wave;
   if (k < k1) {
@@ -1033,7 +1052,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   }
   __syncthreads();
   const size_t tiles = (size_t)g.a_nty * g.a_ntx;
-  float* o = outp + ((size_t)blockIdx.z * tiles + (size_t)blockIdx.y * g.a_ntx + blockIdx.x) * (size_t)(EY * EX);
+  float* o = outp + ((size_t)bz * tiles + (size_t)by * g.a_ntx + bx) * (size_t)(EY * EX);
   for (int rr = wave; rr < EY; rr += 4)
     for (int c = lane; c < EX; c += 64) o[rr * EX + c] = (float)(int)acc[rr * kColPitch + c] * invS;
 }
