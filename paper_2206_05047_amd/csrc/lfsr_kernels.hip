@@ -1574,7 +1574,9 @@ __global__ __launch_bounds__(kThreads, 6) void k_hpstrip(Geom g, const float* __
   constexpr int HS = kTvTileY / 4, LXd = kTvTileX + 2 * RW, LYd = kTvTileY + 2 * RW;
   extern __shared__ float2 smem_f2[];
   float2* pm = smem_f2;  // [LYd][LXd] (p, m^2), zero outside the image
-  const int X0 = blockIdx.x * kTvTileX, Y0 = blockIdx.y * kTvTileY;
+  int bx, by, bz;
+  xcd_block3(bx, by, bz);
+  const int X0 = bx * kTvTileX, Y0 = by * kTvTileY;
   const int tid = threadIdx.x;
   {
     constexpr int n = LYd * LXd, BATCH = 4;
