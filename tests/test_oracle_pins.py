@@ -481,3 +481,69 @@ def test_admm_resume_equals_uninterrupted():
     o.iterate(b, y, disp, count=4)
     for key in ("x", "wD", "wS", "m"):
         np.testing.assert_array_equal(a[key], b[key])
+
+
+def _edge_weight_closed_form(x, sigma_e, occ):
+    """sec 3.4 edge weight read with a decreasing exponent: forward differences,
+    zero at the last row / column, times the occlusion map."""
+    gx = np.zeros_like(x)
+    gy = np.zeros_like(x)
+    gx[:, :-1] = x[:, 1:] - x[:, :-1]
+    gy[:-1, :] = x[1:, :] - x[:-1, :]
+    return np.exp(-(gx ** 2 + gy ** 2) / sigma_e) * occ
+
+
+def test_reweighted_schedule_recomputes_weights_from_previous_iterate():
+    """sec 7.1: with reweighting the edge weight is recomputed at every ADMM
+    iteration.  The reading is that iteration n takes m = w_e(x^(n-1)) * w_o
+    and holds it through its z/w-steps and its CG x-step.  The pin replays
+    the six iterations one at a time with reweighting switched off, setting m
+    each time from the closed form of the weight at the current iterate.  The
+    one-call reweighted run must match it at every step.  Its J_n must also be
+    the cost at x^(n-1) under that m.  If the oracle froze m after the first
+    iteration, or took it from the wrong iterate, this fails from n = 2 on."""
+    kw = dict(sy=6, sx=6, win=3, sigma_e=0.05, lambda1=2.0, lambda2=1.0, theta=4.0)
+    o_rw = _o(reweight=1, **kw)
+    o_fix = _o(reweight=0, **kw)
+    y, disp = _problem(o_rw, 31, noise=0.1)
+    occ = _rng(32).uniform(0.2, 1.0, size=o_rw.hr_shape)
+
+    a = o_rw.init_state(y)
+    stats_a = o_rw.iterate(a, y, disp, occ=occ, count=6)
+
+    b = o_fix.init_state(y)
+    xs, ms = [], []
+    stats_b = np.zeros_like(stats_a)
+    for n in range(1, 7):
+        xs.append(b["x"].copy())
+        b["m"][...] = _edge_weight_closed_form(b["x"], o_fix.pb.sigma_e, occ)
+        ms.append(b["m"].copy())
+        b["n"] = n - 1
+        stats_b[n - 1] = o_fix.iterate(b, y, disp, occ=occ, count=1)[0]
+        # the replay must not have touched m for n >= 2 (reweighting is off)
+        if n >= 2:
+            np.testing.assert_array_equal(b["m"], ms[-1])
+
+    np.testing.assert_allclose(a["x"], b["x"], rtol=0, atol=1e-11 * np.abs(b["x"]).max())
+    np.testing.assert_allclose(stats_a[:, :2], stats_b[:, :2], rtol=1e-10)
+    np.testing.assert_allclose(a["m"], ms[-1], rtol=1e-12, atol=0)
+    for n in range(1, 7):
+        j_ref = o_fix.objective(y, disp, ms[n - 1], xs[n - 1])
+        assert stats_a[n - 1, 0] == pytest.approx(j_ref, rel=1e-10), n
+    # the weights really change over the iterations (otherwise the pin is void)
+    assert np.abs(ms[-1] - ms[0]).max() > 1e-3
+
+
+def test_fixed_weights_keep_the_first_iterations_map():
+    """reweight = 0: m = w_e(x^0) * w_o is computed at n = 1 only and kept."""
+    kw = dict(sy=6, sx=6, win=3, sigma_e=0.05, lambda1=2.0, lambda2=1.0, theta=4.0, reweight=0)
+    o = _o(**kw)
+    y, disp = _problem(o, 33, noise=0.1)
+    occ = _rng(34).uniform(0.2, 1.0, size=o.hr_shape)
+    st = o.init_state(y)
+    m0 = _edge_weight_closed_form(st["x"], o.pb.sigma_e, occ)
+    x0 = st["x"].copy()
+    stats = o.iterate(st, y, disp, occ=occ, count=6)
+    np.testing.assert_allclose(st["m"], m0, rtol=1e-12, atol=0)
+    assert np.abs(st["x"] - x0).max() > 1e-3
+    assert stats[5, 0] != stats[0, 0]
