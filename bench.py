@@ -76,8 +76,58 @@ def traffic_from_profiles(kind):
     return k.get("hbm_bytes_per_launch")
 
 
+def probe_ops(name, reps, which):
+    """Counter-run driver: the forward, adjoint and normal operators of a
+    workload on seeded random inputs, `reps` launches of each selected kind."""
+    import numpy as np
+    import torch
+
+    from paper_2206_05047_amd import lfsr, synth
+
+    cfg = synth.config(name)
+    sc = synth.make_scene(cfg)
+    s = lfsr.Solver(lfsr.make_params(cfg, disp_bound=float(np.abs(sc["disp"]).max())))
+    g = torch.Generator(device="cuda").manual_seed(7)
+    d = torch.from_numpy(sc["disp"]).cuda()
+    x = torch.rand(s.H, s.W, device="cuda", generator=g)
+    m = torch.rand(s.H, s.W, device="cuda", generator=g)
+    e = torch.randn(s.sk, cfg["sy"], cfg["sx"], device="cuda", generator=g)
+    out = torch.empty(s.H, s.W, device="cuda")
+    lr = torch.empty_like(e)
+    for _ in range(reps):
+        if which in ("all", "adj"):
+            s.lfsr_adjoint(e, d, out=out)
+        if which in ("all", "fwd"):
+            s.lfsr_forward(x, d, out=lr)
+        if which in ("all", "hp"):
+            s.lfsr_normal(x, d, m, out=out)
+    torch.cuda.synchronize()
+    log(f"[probe] ops {name} x{reps} {which} done")
+
+
+def probe_copy(nbytes, reps):
+    """Counter calibration: `reps` plain device copies of `nbytes` bytes.  The
+    FETCH_SIZE / WRITE_SIZE readings of one copy, against its known 2 x nbytes
+    of traffic, turn the counters of any other kernel into HBM bytes."""
+    import torch
+
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"[probe] copy {n * 4} bytes x{reps} done")
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--probe", choices=["ops", "copy"], default=None,
+                    help="counter-run drivers instead of the benchmark: 'ops' launches operators of --config "
+                         "(--probe-which fwd|adj|hp|all), 'copy' the plain-copy calibration (--probe-bytes)")
+    ap.add_argument("--probe-which", default="all")
+    ap.add_argument("--probe-reps", type=int, default=3)
+    ap.add_argument("--probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -91,6 +141,10 @@ def main():
                          "currently disabled and reports an error)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="serving arrival rate, jobs/s")
     args = ap.parse_args()
+    if args.probe == "ops":
+        return probe_ops(args.config, args.probe_reps, args.probe_which)
+    if args.probe == "copy":
+        return probe_copy(args.probe_bytes, args.probe_reps)
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(a multi-GPU split into HR row bands is not built).", file=sys.stderr)

@@ -113,19 +113,32 @@ typedef struct {
 } lfsr_stats;
 
 /* Bytes of device workspace a handle with these parameters needs; 0 if the
- * parameters are invalid (lfsr_last_error(NULL) says why). Host-only. */
+ * parameters are invalid (lfsr_last_error(NULL) says why). Host-only.
+ * The workspace holds the state of the ADMM iteration of sec 5, Algorithm 1
+ * (x, the dual fields w_D and w_S, the weight map, the CG vectors of
+ * Algorithm 2) for the problem of sec 3.1 / sec 4 that the parameters
+ * describe; with 16-bit storage its dominant fields take half the bytes. */
 size_t lfsr_workspace_bytes(const lfsr_params* p);
 
 /* Validate p and build a handle over the caller's workspace (d_workspace, at
  * least lfsr_workspace_bytes(p) bytes, 256-byte aligned).  Host-only: touches
- * no device memory. */
+ * no device memory.  The handle fixes one instance of the problem of sec 3.1
+ * and sec 4 (angular grid, LR size, scale, blur, fidelity weights, NLTV
+ * window and weights) and the solver settings of sec 5 (penalty vartheta,
+ * N ADMM iterations, K CG steps, CG tolerance tau).  Errors: LFSR_EINVAL
+ * (bad parameter or alignment, *out = NULL), LFSR_ENOMEM (workspace NULL or
+ * too small). */
 lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, lfsr_handle** out);
 
-/* Release the handle (NULL-safe).  Does not free the workspace. */
+/* Release the handle of a problem instance (sec 3.1 / sec 4) created by
+ * lfsr_create (NULL-safe).  Does not free the workspace and waits for
+ * nothing: work already enqueued on a stream keeps using the workspace, so
+ * the caller frees it only after that work has completed. */
 void lfsr_destroy(lfsr_handle* h);
 
 /* Text of the last error on h, or of the calling thread's last handle-less
- * error when h is NULL.  Never NULL. */
+ * error when h is NULL.  Never NULL.  Parameter errors name the field of the
+ * problem statement (sec 3.1, sec 4, sec 5) that is out of range. */
 const char* lfsr_last_error(const lfsr_handle* h);
 
 /* Complete solve (Algorithm 1): lfsr_init + lfsr_iterate(admm_iters) + copy
