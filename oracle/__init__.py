@@ -85,6 +85,7 @@ def _load():
         "orc_soft_threshold": ([ctypes.c_double, ctypes.c_double], ctypes.c_double),
         "orc_admm_iterate": ([P, D, D, D, D, D, D, D, I, I, D], None),
         "orc_objective": ([P, D, D, D, D], ctypes.c_double),
+        "orc_occlusion_weight": ([P, D, D, ctypes.c_double, ctypes.c_double, D], None),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -289,6 +290,15 @@ class Oracle:
         lr = _f64(lr_ref, (self.pb.sy, self.pb.sx))
         out = np.zeros(self.hr_shape)
         self.lib.orc_bicubic(self._pp, _d(lr), _d(out))
+        return out
+
+    def occlusion_weight(self, y, disp, sigma_o1, sigma_o2):
+        """Occlusion weight w_o [H][W] (sec 3.4, eq. weight_occ) from the LR
+        views and the reference view's disparity map."""
+        y = _f64(y, self.lr_shape)
+        out = np.zeros(self.hr_shape)
+        self.lib.orc_occlusion_weight(self._pp, _d(y), _d(self._disp(disp)), ctypes.c_double(sigma_o1),
+                                      ctypes.c_double(sigma_o2), _d(out))
         return out
 
     def x0(self, y):

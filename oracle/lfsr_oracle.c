@@ -31,6 +31,8 @@
  *     else 0; V_d(z) = c_d m(z), c_d = exp(-|d|^2/sigma_s),
  *     m = w_e * w_o, w_e(z) = exp(-|grad x(z)|^2/sigma_e) with forward
  *     differences (zero at the last row/column)                       (sec 3.4, 4.1).
+ *   - The occlusion weight w_o (eq. weight_occ) is computed from the LR views
+ *     and the reference view's disparity map by orc_occlusion_weight (below). 
  *   - The ADMM loop is the reordered one of sec 5, Algorithm 1, in the
  *     unscaled per-block form (valid for lambda2 = 0 as well), with the x-step
  *     solved by the conjugate-gradient loop of Algorithm 2 on the normal
@@ -412,6 +414,65 @@ void orc_bicubic(const orc_params* p, const double* lr, double* out) {
         }
       out[Y * W + X] = acc;
     }
+}
+
+/* ------------------------------------------------------------ occlusion weight */
+
+/* sec 3.4, eq. (weight_occ): w_o(z) = exp(-b(z)^2 / (2 s1^2)) exp(-p(z)^2 / (2 s2^2)).
+ *   b: one-sided divergence of the reference view's disparity map w: the sum
+ *      of its two forward differences (zero at the last column / row), kept
+ *      where it is negative (occluding boundaries) and 0 elsewhere.
+ *   p: projection error between the reference view and the other views
+ *      brought back to it.  L_i is the bicubic up-sampling of y_i (the x0
+ *      operator above); view i's sample of reference pixel z sits at
+ *      z - theta_i w(z) (the inverse of the forward warp, which reads the
+ *      reference at z + theta_i w(z)), read bilinearly with the position
+ *      clamped to the image; p(z)^2 is the mean of (L_ref(z) - L_i(.))^2 over
+ *      the views i other than the reference (0 with a single view).
+ * s1 or s2 infinite: that factor is 1. */
+void orc_occlusion_weight(const orc_params* p, const double* y, const double* disp, double s1, double s2,
+                          double* out) {
+  const int64_t H = hr_h(p), W = hr_w(p), n = n_hr(p), q = n_lr(p);
+  const int sk = n_views(p), kref = (p->U / 2) * p->V + p->V / 2;
+  const double* w = disp_of(p, disp, kref);
+  double* l0 = (double*)malloc(sizeof(double) * n);
+  double* li = (double*)malloc(sizeof(double) * n);
+  double* acc = (double*)calloc((size_t)n, sizeof(double));
+  orc_bicubic(p, y + (int64_t)kref * q, l0);
+  for (int k = 0; k < sk; ++k) {
+    if (k == kref) continue;
+    int tau, rho;
+    orc_view_offset(p, k, &tau, &rho);
+    orc_bicubic(p, y + (int64_t)k * q, li);
+    for (int64_t Y = 0; Y < H; ++Y)
+      for (int64_t X = 0; X < W; ++X) {
+        double py = (double)Y - tau * w[Y * W + X], px = (double)X - rho * w[Y * W + X];
+        if (py < 0.0) py = 0.0;
+        if (py > (double)(H - 1)) py = (double)(H - 1);
+        if (px < 0.0) px = 0.0;
+        if (px > (double)(W - 1)) px = (double)(W - 1);
+        const int64_t i0 = (int64_t)floor(py), j0 = (int64_t)floor(px);
+        const int64_t i1 = i0 + 1 < H ? i0 + 1 : H - 1, j1 = j0 + 1 < W ? j0 + 1 : W - 1;
+        const double fy = py - i0, fx = px - j0;
+        const double v = (1.0 - fy) * ((1.0 - fx) * li[i0 * W + j0] + fx * li[i0 * W + j1]) +
+                         fy * ((1.0 - fx) * li[i1 * W + j0] + fx * li[i1 * W + j1]);
+        const double d = l0[Y * W + X] - v;
+        acc[Y * W + X] += d * d;
+      }
+  }
+  for (int64_t Y = 0; Y < H; ++Y)
+    for (int64_t X = 0; X < W; ++X) {
+      const double gx = X + 1 < W ? w[Y * W + X + 1] - w[Y * W + X] : 0.0;
+      const double gy = Y + 1 < H ? w[(Y + 1) * W + X] - w[Y * W + X] : 0.0;
+      const double b = gx + gy < 0.0 ? gx + gy : 0.0;
+      const double p2 = sk > 1 ? acc[Y * W + X] / (sk - 1) : 0.0;
+      const double f1 = isinf(s1) ? 1.0 : exp(-b * b / (2.0 * s1 * s1));
+      const double f2 = isinf(s2) ? 1.0 : exp(-p2 / (2.0 * s2 * s2));
+      out[Y * W + X] = f1 * f2;
+    }
+  free(l0);
+  free(li);
+  free(acc);
 }
 
 /* ------------------------------------------------------------ reductions */

@@ -547,3 +547,94 @@ def test_fixed_weights_keep_the_first_iterations_map():
     np.testing.assert_allclose(st["m"], m0, rtol=1e-12, atol=0)
     assert np.abs(st["x"] - x0).max() > 1e-3
     assert stats[5, 0] != stats[0, 0]
+
+
+# ---------------------------------------------------------------- occlusion weight (sec 3.4, eq. weight_occ)
+
+def test_occlusion_weight_step_disparity_closed_form():
+    """Constant views (no projection error): w_o = exp(-b^2/(2 s1^2)) where b
+    is the negative part of the forward-difference divergence of the map.  A
+    drop of D at column c gives b = -D on column c-1; a drop of E at row r
+    gives b = -E on row r-1; where both meet, b = -(D+E); a rise gives 1.
+    Fails for backward differences, a dropped sign clip, or a wrong axis."""
+    o = _o(zeta=1, sy=9, sx=11)
+    H, W = o.hr_shape
+    y = np.full(o.lr_shape, 0.4)
+    s1 = 0.7
+    D, E = 0.9, 0.5
+    d = np.full((H, W), 1.2)
+    d[:, 6:] -= D
+    d[5:, :] -= E
+    b = np.zeros((H, W))
+    b[:, 5] -= D
+    b[4, :] -= E
+    ref = np.exp(-b ** 2 / (2 * s1 ** 2))
+    np.testing.assert_allclose(o.occlusion_weight(y, d, s1, np.inf), ref, rtol=0, atol=1e-14)
+    rise = np.full((H, W), -0.3)
+    rise[:, 6:] += D
+    rise[5:, :] += E
+    np.testing.assert_allclose(o.occlusion_weight(y, rise, s1, 0.3), 1.0, rtol=0, atol=1e-14)
+
+
+def test_occlusion_weight_intensity_offsets_closed_form():
+    """Zero disparity, views = one LR image + a constant c_k per view: the
+    bicubic up-sampling is linear and keeps constants, so the projection error
+    of view k is c_ref - c_k everywhere and w_o = exp(-mean_k (c_ref - c_k)^2
+    / (2 s2^2)) with the mean over the views other than the reference."""
+    o = _o(U=3, V=5, zeta=3)
+    rng = _rng(41)
+    base = rng.uniform(0, 1, (o.pb.sy, o.pb.sx))
+    c = rng.uniform(-0.3, 0.3, o.pb.sk)
+    y = base[None] + c[:, None, None]
+    kref = (o.pb.U // 2) * o.pb.V + o.pb.V // 2
+    p2 = np.mean([(c[kref] - c[k]) ** 2 for k in range(o.pb.sk) if k != kref])
+    s2 = 0.25
+    got = o.occlusion_weight(y, np.zeros(o.hr_shape), np.inf, s2)
+    np.testing.assert_allclose(got, np.exp(-p2 / (2 * s2 ** 2)), rtol=1e-12, atol=0)
+
+
+def test_occlusion_weight_consistent_scene_is_one_in_the_interior():
+    """Scale 1, constant integer disparity, views made as exact shifts of one
+    image by the forward model's convention (view k at u shows the reference
+    at u + theta_k w): every view brought back to the reference matches it
+    wherever the shifted position stays in the image, so w_o = 1 there.
+    Fails for the forward instead of the inverse warp (a doubled shift)."""
+    o = _o(U=3, V=3, zeta=1, sy=12, sx=13)
+    H, W = o.hr_shape
+    rng = _rng(42)
+    x = ndimage.gaussian_filter(rng.uniform(0, 1, (H, W)), 1.0)
+    w = 1
+    y = np.zeros(o.lr_shape)
+    for k in range(o.pb.sk):
+        tau, rho = o.view_offset(k)
+        xp = np.pad(x, 2, mode="edge")
+        y[k] = xp[2 + tau * w:2 + tau * w + H, 2 + rho * w:2 + rho * w + W]
+    got = o.occlusion_weight(y, np.full((H, W), float(w)), np.inf, 0.05)
+    np.testing.assert_allclose(got[1:-1, 1:-1], 1.0, rtol=0, atol=1e-13)
+    assert got.min() < 0.99  # the border rows/columns do see the edge padding
+
+
+def test_occlusion_weight_sampling_equals_scipy_map_coordinates():
+    """The projection error's sampling step against scipy: view k's bicubic
+    up-sampling read with map_coordinates(order=1, mode='nearest') (linear
+    interpolation, clamp-to-edge) at z - theta_k w(z), on a smooth map at
+    scale 2 (the bicubic step itself is pinned above)."""
+    o = _o(U=3, V=3, zeta=2, sy=8, sx=9)
+    rng = _rng(43)
+    y = rng.uniform(0, 1, o.lr_shape)
+    d = _disp_smooth(o, rng, amp=1.6)
+    H, W = o.hr_shape
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    kref = (o.pb.U // 2) * o.pb.V + o.pb.V // 2
+    l0 = o.bicubic(y[kref])
+    acc = np.zeros((H, W))
+    for k in range(o.pb.sk):
+        if k == kref:
+            continue
+        tau, rho = o.view_offset(k)
+        s = ndimage.map_coordinates(o.bicubic(y[k]), [yy - tau * d, xx - rho * d], order=1, mode="nearest")
+        acc += (l0 - s) ** 2
+    p2 = acc / (o.pb.sk - 1)
+    s2 = 0.2
+    got = o.occlusion_weight(y, d, np.inf, s2)
+    np.testing.assert_allclose(got, np.exp(-p2 / (2 * s2 ** 2)), rtol=1e-11, atol=1e-14)
