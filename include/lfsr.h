@@ -200,6 +200,23 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
 lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_occ, float* d_m_out,
                              void* hip_stream);
 
+/* sec 3.4, eq. (weight_occ): the occlusion weight
+ *   d_occ_out = exp(-b^2 / (2 sigma_o1^2)) * exp(-p^2 / (2 sigma_o2^2))   [H][W]
+ * from the LR views d_lr [s_k][lr_h][lr_w] and the reference view's disparity
+ * map d_disp [H][W], ready to pass as d_occ to lfsr_init / lfsr_solve.
+ *   b: the one-sided divergence of the disparity map, the sum of its two
+ *      forward differences (zero at the last column / row), where negative
+ *      (occluding boundaries), else 0;
+ *   p: the projection error, p^2 = mean over the views k other than the
+ *      reference of (L_ref(z) - L_k(z - theta_k disp(z)))^2, L the bicubic
+ *      up-sampling of a view (as for x0), read bilinearly at the position
+ *      clamped to the image (z - theta_k disp(z) is where view k shows the
+ *      reference pixel z under the forward warp).
+ * sigma_o1, sigma_o2 > 0; +INF switches that factor off.  Uses the handle's
+ * work buffers (must not overlap an iteration); FP32. */
+lfsr_status lfsr_occlusion_weight(lfsr_handle* h, const float* d_lr, const float* d_disp, float sigma_o1,
+                                  float sigma_o2, float* d_occ_out, void* hip_stream);
+
 /* sec 5: bicubic up-sampling of one LR view d_lr_view [lr_h][lr_w] to [H][W]
  * (the x0 of lfsr_init). */
 lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out, void* hip_stream);

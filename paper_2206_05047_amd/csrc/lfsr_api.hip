@@ -311,6 +311,47 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   h->n_done += 1;
 }
 
+// The adjoint's fixed-point scale uses per-block contribution counts of the
+// disparity map bound by lfsr_init.  An operator call with another map
+// recounts for its own map; put the bound map's counts back afterwards.
+void restore_counts(lfsr_handle* h, const float* d_disp, hipStream_t s) {
+  if (h->disp && h->disp != d_disp) launch_adjcount(h->plan.g, h->disp, s, h->b);
+}
+
+// Carve a workspace into the buffers of a handle (the layout of make_plan).
+void bind_workspace(lfsr_handle* h, const lfsr_params* p, const Plan& pl, char* w) {
+  h->prm = *p;
+  h->plan = pl;
+  h->ws = w;
+  h->b.sc = (DevScalars*)(w + pl.off_sc);
+  h->b.st = p->storage;
+  h->b.x = w + pl.off_x;
+  h->b.dx = p->storage == LFSR_F32 ? nullptr : (float*)(w + pl.off_dx);
+  h->b.m = (float*)(w + pl.off_m);
+  h->b.vs = (float*)(w + pl.off_vs);
+  h->b.r = (float*)(w + pl.off_r);
+  h->b.pv = (float*)(w + pl.off_pv);
+  h->b.hp = (float*)(w + pl.off_hp);
+  h->b.wD = w + pl.off_wd;
+  h->b.wS[0] = w + pl.off_ws0;
+  h->b.wS[1] = w + pl.off_ws1;
+  h->b.lr = w + pl.off_lr;
+  h->b.adj = (float*)(w + pl.off_adj);
+  h->b.p_wzd = (double*)(w + pl.off_pwzd);
+  h->b.p_tv = (double*)(w + pl.off_ptv);
+  h->b.p_rr[0] = (double*)(w + pl.off_prr0);
+  h->b.p_rr[1] = (double*)(w + pl.off_prr1);
+  h->b.p_php = (double*)(w + pl.off_pphp);
+  h->b.p_max = (float*)(w + pl.off_pmax);
+  h->b.p_cnt = (int*)(w + pl.off_pcnt);
+  h->b.stats = (double*)(w + pl.off_stats);
+  h->n_done = 0;
+  h->bound = false;
+  h->broken = false;
+  h->y = h->disp = h->occ = nullptr;
+  h->err = "no error";
+}
+
 }  // namespace
 
 extern "C" {
@@ -338,36 +379,7 @@ lfsr_status lfsr_create(const lfsr_params* p, void* d_workspace, size_t bytes, l
                    "workspace too small: need " + std::to_string(pl.bytes) + " bytes, got " + std::to_string(bytes));
   lfsr_handle* h = new (std::nothrow) lfsr_handle();
   if (!h) return set_err(nullptr, LFSR_ENOMEM, "host allocation of the handle failed");
-  h->prm = *p;
-  h->plan = pl;
-  h->ws = (char*)d_workspace;
-  char* w = h->ws;
-  h->b.sc = (DevScalars*)(w + pl.off_sc);
-  h->b.st = p->storage;
-  h->b.x = w + pl.off_x;
-  h->b.dx = p->storage == LFSR_F32 ? nullptr : (float*)(w + pl.off_dx);
-  h->b.m = (float*)(w + pl.off_m);
-  h->b.vs = (float*)(w + pl.off_vs);
-  h->b.r = (float*)(w + pl.off_r);
-  h->b.pv = (float*)(w + pl.off_pv);
-  h->b.hp = (float*)(w + pl.off_hp);
-  h->b.wD = w + pl.off_wd;
-  h->b.wS[0] = w + pl.off_ws0;
-  h->b.wS[1] = w + pl.off_ws1;
-  h->b.lr = w + pl.off_lr;
-  h->b.adj = (float*)(w + pl.off_adj);
-  h->b.p_wzd = (double*)(w + pl.off_pwzd);
-  h->b.p_tv = (double*)(w + pl.off_ptv);
-  h->b.p_rr[0] = (double*)(w + pl.off_prr0);
-  h->b.p_rr[1] = (double*)(w + pl.off_prr1);
-  h->b.p_php = (double*)(w + pl.off_pphp);
-  h->b.p_max = (float*)(w + pl.off_pmax);
-  h->b.p_cnt = (int*)(w + pl.off_pcnt);
-  h->b.stats = (double*)(w + pl.off_stats);
-  h->n_done = 0;
-  h->bound = false;
-  h->broken = false;
-  h->err = "no error";
+  bind_workspace(h, p, pl, (char*)d_workspace);
   *out = h;
   return LFSR_OK;
 }
@@ -536,6 +548,7 @@ lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp,
   launch_adjcount(g, d_disp, S(hip_stream), h->b);
   launch_adjoint(g, d_lr, kStF32, d_disp, S(hip_stream), h->b, 0, npmax);
   launch_merge(g, d_hr_out, S(hip_stream), h->b, 0);
+  restore_counts(h, d_disp, S(hip_stream));
   return check_hip(h, "lfsr_adjoint");
 }
 
@@ -553,6 +566,7 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   const int fuse = merge_fusable(g) ? 1 : 0;
   if (!fuse) launch_merge(g, d_out, s, h->b, 0);
   launch_hp(g, d_p, d_m, d_out, s, h->b, 0, 0, fuse);
+  restore_counts(h, d_disp, s);
   return check_hip(h, "lfsr_normal");
 }
 
@@ -562,6 +576,31 @@ lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_oc
   if (!d_x || !d_m_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
   launch_edge(h->plan.g, d_x, kStF32, d_occ, d_m_out, S(hip_stream), h->b, 0);
   return check_hip(h, "lfsr_edge_weight");
+}
+
+lfsr_status lfsr_occlusion_weight(lfsr_handle* h, const float* d_lr, const float* d_disp, float sigma_o1,
+                                  float sigma_o2, float* d_occ_out, void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!d_lr || !d_disp || !d_occ_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  if (!(sigma_o1 > 0.f) || !(sigma_o2 > 0.f))
+    return set_err(h, LFSR_EINVAL, "sigma_o1 and sigma_o2 must be > 0 (+INF switches a factor off)");
+  const Geom& g = h->plan.g;
+  hipStream_t s = S(hip_stream);
+  // the CG vectors are free outside an iteration: the up-sampled reference
+  // view, the up-sampled view k and the running sum of squared errors
+  float *lref = h->b.r, *lk = h->b.pv, *acc = h->b.hp;
+  launch_bicubic(g, d_lr + (size_t)g.kref * g.q, lref, s);
+  launch_fill(acc, g.p, 0.f, s);
+  for (int k = 0; k < g.sk; ++k) {
+    if (k == g.kref) continue;
+    launch_bicubic(g, d_lr + (size_t)k * g.q, lk, s);
+    launch_occ_acc(g, lref, lk, d_disp, k, acc, s);
+  }
+  const float c1 = std::isinf(sigma_o1) ? 0.f : (float)(0.5 / ((double)sigma_o1 * sigma_o1));
+  const float c2 = std::isinf(sigma_o2) ? 0.f : (float)(0.5 / ((double)sigma_o2 * sigma_o2));
+  launch_occ_final(g, d_disp, acc, g.sk > 1 ? (float)(1.0 / (g.sk - 1)) : 0.f, c1, c2, d_occ_out, s);
+  return check_hip(h, "lfsr_occlusion_weight");
 }
 
 lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out, void* hip_stream) {

@@ -171,6 +171,11 @@ void launch_to_float(const void* in, int st, float* out, long long n, hipStream_
 void launch_from_float(const float* in, void* out, int st, long long n, hipStream_t s);
 void launch_zero(void* p, int st, long long n, hipStream_t s);
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s);
+// occlusion weight: acc += squared projection error of view k; then the weight
+void launch_occ_acc(const Geom& g, const float* lref, const float* lk, const float* disp, int k, float* acc,
+                    hipStream_t s);
+void launch_occ_final(const Geom& g, const float* disp, const float* acc, float inv_views, float c1, float c2,
+                      float* out, hipStream_t s);
 void launch_check(const Geom& g, const float* y, const float* disp, const float* occ, hipStream_t s, const Bufs& b);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_reset(int n_done, hipStream_t s, const Bufs& b);

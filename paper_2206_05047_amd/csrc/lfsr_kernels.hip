@@ -1848,6 +1848,48 @@ __global__ __launch_bounds__(kThreads) void k_bicubic(Geom g, const float* __res
   }
 }
 
+// Occlusion weight (sec 3.4, eq. weight_occ), projection-error part: for one
+// view k, acc += (L_ref(z) - L_k(z - theta_k w(z)))^2 at every HR pixel z, with
+// L_ref, L_k the bicubic up-sampled views (the x0 operator) and L_k read
+// bilinearly at the position clamped to the image.
+__global__ __launch_bounds__(kThreads) void k_occ_acc(Geom g, const float* __restrict__ lref,
+                                                      const float* __restrict__ lk, const float* __restrict__ disp,
+                                                      float tau, float rho, float* __restrict__ acc) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
+    const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
+    const float w = disp[o];
+    const float py = fminf(fmaxf((float)Y - tau * w, 0.f), (float)(g.H - 1));
+    const float px = fminf(fmaxf((float)X - rho * w, 0.f), (float)(g.W - 1));
+    const int i0 = (int)floorf(py), j0 = (int)floorf(px);
+    const int i1 = min(i0 + 1, g.H - 1), j1 = min(j0 + 1, g.W - 1);
+    const float fy = py - (float)i0, fx = px - (float)j0;
+    const float* r0 = lk + (size_t)i0 * g.W;
+    const float* r1 = lk + (size_t)i1 * g.W;
+    const float top = fmaf(fx, r0[j1] - r0[j0], r0[j0]);
+    const float bot = fmaf(fx, r1[j1] - r1[j0], r1[j0]);
+    const float d = lref[o] - fmaf(fy, bot - top, top);
+    acc[o] = fmaf(d, d, acc[o]);
+  }
+}
+
+// Occlusion weight, final: w_o = exp(-b^2 c1) exp(-(acc / nviews) c2) with b
+// the negative part of the forward-difference divergence of the disparity
+// map (zero differences at the last row / column); c = 1/(2 sigma^2), 0 for
+// a factor that is switched off.
+__global__ __launch_bounds__(kThreads) void k_occ_final(Geom g, const float* __restrict__ disp,
+                                                        const float* __restrict__ acc, float inv_views, float c1,
+                                                        float c2, float* __restrict__ out) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
+    const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
+    const float w = disp[o];
+    const float gx = X + 1 < g.W ? disp[o + 1] - w : 0.f;
+    const float gy = Y + 1 < g.H ? disp[o + g.W] - w : 0.f;
+    const float b = fminf(gx + gy, 0.f);
+    const float p2 = acc[o] * inv_views;
+    out[o] = expf(-b * b * c1) * expf(-p2 * c2);
+  }
+}
+
 // Input check: non-finite LR / disparity / occlusion values (bit 0) and
 // |disp| > disp_bound (bit 1).
 __global__ __launch_bounds__(kThreads) void k_check(Geom g, const float* __restrict__ y, const float* __restrict__ disp,
@@ -2345,6 +2387,18 @@ void launch_zero(void* p, int st, long long n, hipStream_t s) {
 
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_bicubic, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, lrv, out);
+}
+
+void launch_occ_acc(const Geom& g, const float* lref, const float* lk, const float* disp, int k, float* acc,
+                    hipStream_t s) {
+  const int a = k / g.V, c = k - a * g.V;
+  const float tau = (float)(a - (g.U - 1) / 2), rho = (float)(c - (g.V - 1) / 2);
+  hipLaunchKernelGGL(k_occ_acc, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, lref, lk, disp, tau, rho, acc);
+}
+
+void launch_occ_final(const Geom& g, const float* disp, const float* acc, float inv_views, float c1, float c2,
+                      float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_occ_final, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, disp, acc, inv_views, c1, c2, out);
 }
 
 void launch_check(const Geom& g, const float* y, const float* disp, const float* occ, hipStream_t s, const Bufs& b) {

@@ -25,7 +25,7 @@ EXPORTS = [
     "lfsr_iterate", "lfsr_read_state", "lfsr_write_state", "lfsr_get_stats", "lfsr_forward", "lfsr_adjoint",
     "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic", "lfsr_profile_begin", "lfsr_profile_end",
     "lfsr_pool_create", "lfsr_pool_destroy", "lfsr_pool_last_error", "lfsr_pool_submit", "lfsr_pool_tick",
-    "lfsr_pool_poll", "lfsr_pool_info",
+    "lfsr_pool_poll", "lfsr_pool_info", "lfsr_occlusion_weight",
 ]
 LFSR_K_FORWARD, LFSR_K_ADJOINT, LFSR_K_NLTV, LFSR_K_NORMAL, LFSR_K_CG, LFSR_K_OTHER, LFSR_K_COUNT = range(7)
 KERNEL_KINDS = ["forward", "adjoint", "nltv", "normal", "cg", "other"]
@@ -100,6 +100,8 @@ def load():
     lib.lfsr_normal.restype = I
     lib.lfsr_edge_weight.argtypes = [H, F, F, F, V]
     lib.lfsr_edge_weight.restype = I
+    lib.lfsr_occlusion_weight.argtypes = [H, F, F, ctypes.c_float, ctypes.c_float, F, V]
+    lib.lfsr_occlusion_weight.restype = I
     lib.lfsr_bicubic.argtypes = [H, F, F, V]
     lib.lfsr_bicubic.restype = I
     lib.lfsr_profile_begin.argtypes = [H, ctypes.c_uint32, I]
@@ -277,6 +279,12 @@ class Solver:
         out = self._empty(self.H, self.W) if out is None else out
         self._check(self.lib.lfsr_edge_weight(self.handle, _ptr(x), _ptr(occ), _ptr(out), _stream(stream)),
                     self.handle)
+        return out
+
+    def lfsr_occlusion_weight(self, lr, disp, sigma_o1, sigma_o2, out=None, stream=None):
+        out = self._empty(self.H, self.W) if out is None else out
+        self._check(self.lib.lfsr_occlusion_weight(self.handle, _ptr(lr), _ptr(disp), float(sigma_o1),
+                                                   float(sigma_o2), _ptr(out), _stream(stream)), self.handle)
         return out
 
     def lfsr_bicubic(self, lr_view, out=None, stream=None):

@@ -37,3 +37,24 @@ def rel_err(a, ref):
     ref = np.asarray(ref, np.float64)
     den = np.abs(ref).max()
     return float(np.abs(a - ref).max() / (den if den > 0 else 1.0))
+
+
+def occ_exponent_err(got, ref, s1, s2):
+    """Occlusion weight parity on its exponent E = -log w_o = b^2 c1 + p^2 c2
+    (c = 1/(2 sigma^2)): returns max |E_got - E_ref| / bound.  FP32 bicubic
+    values are within 2.5e-6 of exact (16 Keys taps, sum |weight| < 1.3, on
+    [0,1] data, two of them per difference), so a squared projection error
+    moves by at most 2 |d| 2.5e-6 <= 5e-6 and p^2 (a mean of them) too; b is a
+    difference of two disparity values (relative 1.2e-7, |b| <= 8).  Where
+    the exact weight is below FP32's normal range (E >= 80) the FP32 result
+    may underflow: there it must only be below 1e-34."""
+    c1 = 0.0 if np.isinf(s1) else 0.5 / s1 ** 2
+    c2 = 0.0 if np.isinf(s2) else 0.5 / s2 ** 2
+    bound = 5e-6 * c2 + 2e-6 * 8.0 * c1 + 1e-6
+    got = np.asarray(got, np.float64)
+    er = -np.log(np.asarray(ref, np.float64))
+    deep = er >= 80.0
+    if np.any(got[deep] >= 1e-34):
+        return float("inf")
+    eg = -np.log(np.maximum(got[~deep], 1e-300))
+    return float(np.max(np.abs(eg - er[~deep]), initial=0.0) / bound)

@@ -3,8 +3,9 @@ benchmark times (same parameters, same kernels):
 
 * c2 (5x5 views, 512^2, x2, 50 ADMM iterations): the whole HR result against
   the stored FP64 oracle solve, relative L2 <= 1e-4;
-* c3 (9x9 views, 1152^2, x3, 100 iterations): the result on 65536 seeded
-  pixels against the stored oracle solve, relative L2 <= 1e-4 on the samples;
+* c3 (9x9 views, 1152^2, x3, 100 iterations): the whole HR result against
+  the stored FP64 oracle solve, relative L2 <= 1e-4, and no 64x64 block of
+  it above 1e-3 (a tile, halo or block-order fault is local);
 * c3 single operators and one ADMM iteration against the oracle computed
   here (the duals and the weight map are local, so every element is checked).
 
@@ -19,7 +20,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from helpers import rel_err  # noqa: E402
+from helpers import occ_exponent_err, rel_err  # noqa: E402
 
 import oracle  # noqa: E402
 from paper_2206_05047_amd import synth  # noqa: E402
@@ -91,17 +92,30 @@ def test_c2_full_solve_matches_stored_oracle(lfsr):
     np.testing.assert_allclose(st["hist"][:, 0], g["hist"][:, 0], rtol=1e-4)
 
 
-def test_c3_full_solve_matches_stored_oracle_on_samples(lfsr):
+def _worst_block(x, ref, b=64):
+    """Largest relative L2 error over the b x b blocks of the image."""
+    H, W = ref.shape
+    worst = 0.0
+    for i in range(0, H, b):
+        for j in range(0, W, b):
+            r = ref[i:i + b, j:j + b].astype(np.float64)
+            worst = max(worst, float(np.linalg.norm(x[i:i + b, j:j + b] - r) / max(np.linalg.norm(r), 1e-30)))
+    return worst
+
+
+def test_c3_full_solve_matches_stored_oracle(lfsr):
     c = _case("c3")
     g = _golden("c3", c)
     s = _solver(lfsr, c)
     x, st = s.lfsr_solve(_t(c["y"]), _t(c["sc"]["disp"]))
-    xs = _n(x).ravel()[g["idx"]]
-    err = synth.rel_l2(xs, g["x_samples"])
-    print(f"c3 rel_l2(samples)={err:.3e} psnr={synth.psnr(_n(x), c['sc']['x_gt']):.3f} "
+    x = _n(x)
+    err = synth.rel_l2(x, g["x"])
+    blk = _worst_block(x, g["x"])
+    print(f"c3 rel_l2={err:.3e} worst 64x64 block {blk:.3e} psnr={synth.psnr(x, c['sc']['x_gt']):.3f} "
           f"(oracle {float(g['psnr_gt']):.3f})", flush=True)
     assert err < 1e-4
-    assert abs(np.linalg.norm(_n(x)) - float(g["norm"])) < 1e-4 * float(g["norm"])
+    assert blk < 1e-3
+    assert abs(np.linalg.norm(x) - float(g["norm"])) < 1e-4 * float(g["norm"])
     np.testing.assert_allclose(st["hist"][:, 0], g["hist"][:, 0], rtol=1e-4)
 
 
@@ -121,6 +135,16 @@ def test_c3_operators_match_oracle(lfsr):
     assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.vdot(t_gpu, t_gpu) * np.vdot(e, e))
 
 
+def test_c3_occlusion_weight_matches_oracle(lfsr):
+    c = _case("c3")
+    s = _solver(lfsr, c)
+    got = _n(s.lfsr_occlusion_weight(_t(c["y"]), _t(c["sc"]["disp"]), 0.5, 0.1))
+    ref = c["o"].occlusion_weight(c["y"], c["sc"]["disp"], 0.5, 0.1)
+    err = occ_exponent_err(got, ref, 0.5, 0.1)
+    print(f"c3 w_o exponent error / bound {err:.3f}", flush=True)
+    assert err <= 1.0
+
+
 def test_c3_one_iteration_matches_oracle(lfsr):
     c = _case("c3")
     s = _solver(lfsr, c)
@@ -138,17 +162,17 @@ def test_c3_one_iteration_matches_oracle(lfsr):
 
 @pytest.mark.parametrize("st,tol", [("f16", 2e-3), ("bf16", 1.5e-2)])
 def test_c3_16bit_storage_against_stored_oracle(lfsr, st, tol):
-    """The precision form of the large workload: relative L2 on the samples
-    and PSNR against the ground truth, both against the FP64 oracle (bounds
-    as for the small cases, see test_gpu_precision)."""
+    """The precision form of the large workload: relative L2 over the whole
+    image and PSNR against the ground truth, both against the FP64 oracle
+    (bounds as for the small cases, see test_gpu_precision)."""
     c = _case("c3")
     g = _golden("c3", c)
     bound = float(np.abs(c["sc"]["disp"]).max())
     s = lfsr.Solver(lfsr.make_params(c["cfg"], disp_bound=bound, storage=st))
     x, _ = s.lfsr_solve(_t(c["y"]), _t(c["sc"]["disp"]))
     x = _n(x)
-    err = synth.rel_l2(x.ravel()[g["idx"]], g["x_samples"])
+    err = synth.rel_l2(x, g["x"])
     p16 = synth.psnr(x, c["sc"]["x_gt"])
-    print(f"c3 {st}: rel_l2(samples)={err:.3e} psnr={p16:.3f} (oracle {float(g['psnr_gt']):.3f})", flush=True)
+    print(f"c3 {st}: rel_l2={err:.3e} psnr={p16:.3f} (oracle {float(g['psnr_gt']):.3f})", flush=True)
     assert err < tol
     assert abs(p16 - float(g["psnr_gt"])) <= 0.05

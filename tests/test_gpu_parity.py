@@ -1,13 +1,13 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
 same seeded inputs.  Tolerances are relative to the FP32 arithmetic of the
-kernels: single operators 1e-5 (max-abs relative), whole solves 1e-4 relative
+kernels: single operators 2e-5 (max-abs relative), whole solves 1e-4 relative
 L2 (the bar the method's FP32 solver must meet against the FP64 oracle)."""
 import numpy as np
 import pytest
 
 torch = pytest.importorskip("torch")
 
-from helpers import CASES, disp_bound, make_case, rel_err  # noqa: E402
+from helpers import CASES, disp_bound, make_case, occ_exponent_err, rel_err  # noqa: E402
 
 import oracle  # noqa: E402
 from paper_2206_05047_amd import synth  # noqa: E402
@@ -65,6 +65,64 @@ def test_adjoint_matches_oracle(lfsr, case):
     assert rel_err(got, ref) < OP_TOL
 
 
+def _transpose_footprint(cfg, disp, bound, u_abs):
+    """Per HR pixel z: N(z), the number of (view, pixel, tap) terms of the
+    bilinear transpose W_k^T that land on z, and G(z), the sum over those terms
+    of u_abs[k] at the source pixel.  The tap rows/columns are
+    floor(tau_k * disp) and floor(rho_k * disp) with the float32 product and the
+    disparity clamped to its bound, as the device computes them."""
+    U, V = cfg["U"], cfg["V"]
+    H, W = disp.shape
+    om = np.clip(disp.astype(np.float32), np.float32(-bound), np.float32(bound))
+    Y, X = np.mgrid[0:H, 0:W]
+    N, G = np.zeros((H, W)), np.zeros((H, W))
+    for k in range(U * V):
+        tau, rho = np.float32(k // V - (U - 1) // 2), np.float32(k % V - (V - 1) // 2)
+        iy = Y + np.floor(tau * om).astype(np.int64)
+        ix = X + np.floor(rho * om).astype(np.int64)
+        for dy in (0, 1):
+            for dx in (0, 1):
+                yy, xx = iy + dy, ix + dx
+                ok = (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W)
+                np.add.at(N, (yy[ok], xx[ok]), 1.0)
+                np.add.at(G, (yy[ok], xx[ok]), u_abs[k][ok])
+    return N, G
+
+
+def test_adjoint_high_dynamic_range_elementwise_bound(lfsr, case):
+    """A^T e for e with a few outliers of 1e3 among values of 1e-3.  The
+    adjoint accumulates in integers at a scale set by max |e| (column kernel:
+    each term rounded at 2^(hd + eM - 32), hd = bits of the largest per-cell
+    term count + 1, max |e| < 2^eM; general kernel: truncated at 2^(eM - 30)),
+    so its error is bounded element by element by
+        N(z) * 2^(hd + eM - 32)  +  128 * 2^-24 * G(z),
+    N(z) the number of terms landing on z and G(z) the sum of B^T D^T |e| over
+    their source pixels (FP32 rounding of the terms and of the merge).  The
+    max-normalised check of the other operator tests is also met."""
+    cfg, o = case["cfg"], case["oracle"]
+    s = _solver(lfsr, cfg)
+    rng = np.random.default_rng(21)
+    e = (1e-3 * rng.standard_normal(o.lr_shape)).astype(np.float32)
+    flat = e.reshape(-1)
+    hot = rng.choice(flat.size, size=8, replace=False)
+    flat[hot] = rng.choice([-1e3, 1e3], size=8) * rng.uniform(0.5, 1.0, size=8)
+    got = _n(s.lfsr_adjoint(_t(e), _t(case["disp"])))
+    ref = o.adjoint(e, case["disp"])
+    assert rel_err(got, ref) < OP_TOL
+    u_abs = np.stack([o.blur_t(o.up(np.abs(e[k]))) for k in range(o.pb.sk)])
+    N, G = _transpose_footprint(cfg, case["disp"], disp_bound(cfg), u_abs)
+    eM = int(np.frexp(np.float32(np.abs(e).max()))[1])
+    hd = int(np.frexp(N.max() + 1.0)[1])
+    step = max(2.0 ** (hd + eM - 32), 2.0 ** (eM - 30))
+    bound = N * step + 128 * 2.0 ** -24 * G
+    err = np.abs(got - ref)
+    small = np.abs(ref) < 1e-3 * np.abs(ref).max()
+    print(f"hdr: max err/bound {np.max(err / np.maximum(bound, 1e-30)):.3f}, "
+          f"max rel err where |ref| < 1e-3 max: {np.max(err[small] / np.maximum(np.abs(ref[small]), 1e-30)):.2e}",
+          flush=True)
+    assert np.all(err <= bound)
+
+
 def test_normal_operator_matches_oracle(lfsr, case):
     s = _solver(lfsr, case["cfg"])
     o = case["oracle"]
@@ -115,6 +173,32 @@ def test_edge_weight_and_bicubic_match_oracle(lfsr, case):
     assert rel_err(_n(s.lfsr_edge_weight(_t(x))), o.edge_weight(x)) < OP_TOL
     lr = case["y"][o.pb.sk // 2]
     assert rel_err(_n(s.lfsr_bicubic(_t(lr))), o.bicubic(lr)) < OP_TOL
+
+
+def test_occlusion_weight_matches_oracle(lfsr, case):
+    """w_o (sec 3.4, eq. weight_occ) from the noisy LR views and the case's
+    disparity map, both factors on, and each factor alone."""
+    s = _solver(lfsr, case["cfg"])
+    o = case["oracle"]
+    y, d = _t(case["y"]), _t(case["disp"])
+    for s1, s2 in ((0.5, 0.1), (0.3, np.inf), (np.inf, 0.05)):
+        got = _n(s.lfsr_occlusion_weight(y, d, s1, s2))
+        ref = o.occlusion_weight(case["y"], case["disp"], s1, s2)
+        assert occ_exponent_err(got, ref, s1, s2) <= 1.0, (s1, s2, occ_exponent_err(got, ref, s1, s2))
+
+
+def test_solve_with_the_gpu_occlusion_weight(lfsr):
+    """The whole solve with w_o computed on the GPU against the oracle's solve
+    with the oracle's w_o."""
+    case = make_case(CASES["ragged"])
+    cfg, o = case["cfg"], case["oracle"]
+    s = _solver(lfsr, cfg)
+    y, d = _t(case["y"]), _t(case["disp"])
+    occ = s.lfsr_occlusion_weight(y, d, 0.5, 0.1)
+    x, _ = s.lfsr_solve(y, d, occ=occ)
+    occ_o = o.occlusion_weight(case["y"], case["disp"], 0.5, 0.1)
+    xr, _ = o.solve(case["y"], case["disp"], occ=occ_o)
+    assert synth.rel_l2(_n(x), xr) < SOLVE_TOL
 
 
 def test_one_iteration_state_matches_oracle(lfsr, case):
@@ -241,3 +325,34 @@ def test_input_errors_reported(lfsr):
     with pytest.raises(lfsr.LfsrError) as ei:
         s.lfsr_get_stats()
     assert ei.value.code == lfsr.LFSR_EINVAL
+
+
+def test_operator_calls_keep_the_bound_disparity_counts(lfsr):
+    """lfsr_adjoint / lfsr_normal with another disparity map between lfsr_init
+    and lfsr_iterate must not change what the iteration computes: the
+    adjoint's fixed-point scale depends on per-block contribution counts of
+    the bound map.  The bound map is a sawtooth that folds 13 columns of the
+    outer views onto one (counts one bit above those of a zero map), the
+    operator calls use a zero map; the result must equal a fresh solve bit
+    for bit."""
+    cfg = dict(WIDE, disp_max=3.0)
+    o = oracle.Oracle(cfg)
+    H, W = o.hr_shape
+    X = np.broadcast_to(np.arange(W), (H, W))
+    saw = (-((X % 13) - 6) / 4.0).astype(np.float32)
+    sc = synth.make_scene(cfg)
+    y = synth.degrade(o.forward(sc["x_gt"], saw), synth.make_noise(cfg))
+    zero = np.zeros((H, W), np.float32)
+    rng = np.random.default_rng(6)
+    pv = _t(rng.standard_normal((H, W)))
+    m = _t(rng.uniform(0.2, 1.0, (H, W)))
+    e = _t(rng.standard_normal(o.lr_shape))
+    a = _solver(lfsr, cfg)
+    a.lfsr_init(_t(y), _t(saw))
+    a.lfsr_normal(pv, _t(zero), m)
+    a.lfsr_adjoint(e, _t(zero))
+    a.lfsr_iterate(cfg["n_iter"])
+    got = _n(a.lfsr_read_state()["x"])
+    b = _solver(lfsr, cfg)
+    ref, _ = b.lfsr_solve(_t(y), _t(saw))
+    np.testing.assert_array_equal(got, _n(ref))
