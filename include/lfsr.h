@@ -147,6 +147,26 @@ const char* lfsr_last_error(const lfsr_handle* h);
 lfsr_status lfsr_solve(lfsr_handle* h, const float* d_lr, const float* d_disp, const float* d_occ,
                        const float* d_x0, float* d_hr_out, lfsr_stats* h_stats, void* hip_stream);
 
+/* Variant of lfsr_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): it takes the parameters instead of a handle and runs the same
+ * kernels over a workspace held in a static device array of
+ * LFSR_NOALLOC_MAX_BYTES bytes, one per GPU, resident until the process ends.
+ * It calls no hipMalloc / hipFree and allocates no device memory; the caller
+ * still provides the inputs (layouts as for lfsr_init) and d_hr_out [H][W].
+ * Problems whose lfsr_workspace_bytes exceed LFSR_NOALLOC_MAX_BYTES are
+ * rejected with LFSR_ENOMEM before any work is enqueued; invalid parameters
+ * give LFSR_EINVAL.  Errors are reported through lfsr_last_error(NULL).
+ * Every call on one GPU uses that GPU's one array and leaves its state there
+ * (each call starts from x0 and w = 0 of its own): calls that overlap on one
+ * GPU (two streams, two threads, or a second call before the first one's work
+ * has completed on another stream) race and give wrong results; calls on one
+ * stream are ordered and safe.  Asynchronous on hip_stream unless h_stats is
+ * non-NULL (then it synchronises and fills *h_stats, as lfsr_solve does). */
+#define LFSR_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+lfsr_status lfsr_solve_noalloc(const lfsr_params* p, const float* d_lr, const float* d_disp, const float* d_occ,
+                               const float* d_x0, float* d_hr_out, lfsr_stats* h_stats, void* hip_stream);
+
 /* Bind the inputs (d_lr [s_k][lr_h][lr_w], d_disp [H][W], d_occ [H][W]
  * occlusion weight or NULL = 1) and set the state to x = d_x0 (or, if NULL,
  * the bicubic up-sampling of the centre view: Keys a = -1/2, LR sample (i,j)

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -309,6 +310,42 @@ void enqueue_iteration(lfsr_handle* h, hipStream_t s) {
   if (b.st != kStF32) timed(h, LFSR_K_CG, s, [&] { launch_fold(g, s, b); });
   timed(h, LFSR_K_OTHER, s, [&] { launch_iter_end(g, s, b); });
   h->n_done += 1;
+}
+
+// Workspace of lfsr_solve_noalloc: one array per GPU, resident for the life
+// of the process.  Host code never uses this name as an address (on the host
+// it only identifies the symbol); the device address of each GPU's copy is
+// looked up once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[LFSR_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device); nullptr and *err set on failure.
+void* scratch_ptr(std::string* err) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = "device index beyond the scratch table";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
 }
 
 // The adjoint's fixed-point scale uses per-block contribution counts of the
@@ -661,6 +698,26 @@ lfsr_status lfsr_profile_end(lfsr_handle* h, double* h_total_ms, int32_t* h_laun
     if (h_launches) h_launches[k] = cnt[k];
   }
   return res;
+}
+
+lfsr_status lfsr_solve_noalloc(const lfsr_params* p, const float* d_lr, const float* d_disp, const float* d_occ,
+                               const float* d_x0, float* d_hr_out, lfsr_stats* h_stats, void* hip_stream) {
+  Plan pl;
+  std::string err;
+  if (!make_plan(p, &pl, &err)) return set_err(nullptr, LFSR_EINVAL, err);
+  if (pl.bytes > LFSR_NOALLOC_MAX_BYTES)
+    return set_err(nullptr, LFSR_ENOMEM,
+                   "lfsr_solve_noalloc: the problem needs " + std::to_string(pl.bytes) +
+                       " bytes of workspace, above the static scratch of " + std::to_string(LFSR_NOALLOC_MAX_BYTES) +
+                       " bytes (use lfsr_create + lfsr_solve with a caller workspace)");
+  char* ws = (char*)scratch_ptr(&err);
+  if (!ws) return set_err(nullptr, LFSR_EDEVICE, "lfsr_solve_noalloc: " + err);
+  // a handle for this call only: every kernel gets the scratch pointers by value
+  lfsr_handle h{};
+  bind_workspace(&h, p, pl, ws);
+  const lfsr_status st = lfsr_solve(&h, d_lr, d_disp, d_occ, d_x0, d_hr_out, h_stats, hip_stream);
+  if (st) set_err(nullptr, st, "lfsr_solve_noalloc: " + h.err);
+  return st;
 }
 
 }  // extern "C"

@@ -25,7 +25,8 @@ EXPORTS = [
     "lfsr_iterate", "lfsr_read_state", "lfsr_write_state", "lfsr_get_stats", "lfsr_forward", "lfsr_adjoint",
     "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic", "lfsr_profile_begin", "lfsr_profile_end",
     "lfsr_pool_create", "lfsr_pool_destroy", "lfsr_pool_last_error", "lfsr_pool_submit", "lfsr_pool_tick",
-    "lfsr_pool_poll", "lfsr_pool_info", "lfsr_occlusion_weight",
+    "lfsr_pool_poll", "lfsr_pool_info", "lfsr_solve_noalloc",
+    "lfsr_occlusion_weight",
 ]
 LFSR_K_FORWARD, LFSR_K_ADJOINT, LFSR_K_NLTV, LFSR_K_NORMAL, LFSR_K_CG, LFSR_K_OTHER, LFSR_K_COUNT = range(7)
 KERNEL_KINDS = ["forward", "adjoint", "nltv", "normal", "cg", "other"]
@@ -83,6 +84,8 @@ def load():
     lib.lfsr_last_error.restype = ctypes.c_char_p
     lib.lfsr_solve.argtypes = [H, F, F, F, F, F, ctypes.POINTER(lfsr_stats), V]
     lib.lfsr_solve.restype = I
+    lib.lfsr_solve_noalloc.argtypes = [P, F, F, F, F, F, ctypes.POINTER(lfsr_stats), V]
+    lib.lfsr_solve_noalloc.restype = I
     lib.lfsr_init.argtypes = [H, F, F, F, F, V]
     lib.lfsr_init.restype = I
     lib.lfsr_iterate.argtypes = [H, I, V]
@@ -305,6 +308,33 @@ class Solver:
         cnt = (ctypes.c_int32 * LFSR_K_COUNT)()
         self._check(self.lib.lfsr_profile_end(self.handle, tot, cnt), self.handle)
         return {KERNEL_KINDS[k]: (tot[k], cnt[k]) for k in range(LFSR_K_COUNT)}
+
+
+NOALLOC_MAX_BYTES = 64 << 20  # LFSR_NOALLOC_MAX_BYTES
+
+
+def solve_noalloc(params: lfsr_params, y, disp, occ=None, x0=None, out=None, stats=False, stream=None):
+    """lfsr_solve_noalloc: a complete solve over the library's static per-GPU
+    scratch (no workspace allocation).  Returns (x, stats dict or None)."""
+    lib = load()
+    H, W = params.scale * params.lr_h, params.scale * params.lr_w
+    out = torch.empty((H, W), dtype=torch.float32, device=y.device) if out is None else out
+    st = hist = None
+    if stats:
+        hist = (ctypes.c_double * (params.admm_iters * LFSR_NSTAT))()
+        st = lfsr_stats()
+        st.h_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    code = lib.lfsr_solve_noalloc(ctypes.byref(params), _ptr(y), _ptr(disp), _ptr(occ), _ptr(x0), _ptr(out),
+                                  ctypes.byref(st) if st is not None else None, _stream(stream))
+    if code != LFSR_OK:
+        raise LfsrError(code, last_error())
+    if not stats:
+        return out, None
+    import numpy as np
+    n = min(st.iters_run, params.admm_iters)
+    h = np.frombuffer(hist, dtype=np.float64).reshape(params.admm_iters, LFSR_NSTAT)[:n].copy()
+    return out, {"iters_run": st.iters_run, "cg_steps": st.cg_steps, "objective": st.objective,
+                 "primal_res": st.primal_res, "cg_pi": st.cg_pi, "hist": h}
 
 
 def disp_bound_for(disp, margin=1.0) -> float:
