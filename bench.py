@@ -76,6 +76,41 @@ def traffic_from_profiles(kind):
     return k.get("hbm_bytes_per_launch")
 
 
+def counter_bytes_per_solve(n_iter):
+    """HBM bytes of one solve from the committed FETCH_SIZE / WRITE_SIZE
+    record (copy-calibrated, per kernel): the per-iteration kernels times
+    their launches per iteration, times N, plus the once-per-solve set-up;
+    None if the record is absent or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2206_05047_amd", "csrc", "lfsr_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    per = rec.get("per_solve")
+    if not per or rec.get("kernel_source_sha256") != sha:
+        return None
+    return per["bytes_per_iteration"] * n_iter + per["bytes_setup"]
+
+
+def oracle_one_thread(name, iters):
+    """CPU-only child: the oracle's ADMM iterations on one thread (OMP_NUM_THREADS=1),
+    inputs from the oracle's own forward model; prints seconds per iteration."""
+    import oracle
+    from paper_2206_05047_amd import synth
+
+    cfg = synth.config(name)
+    o = oracle.Oracle(cfg)
+    sc = synth.make_scene(cfg)
+    y = synth.degrade(o.forward(sc["x_gt"], sc["disp"]), synth.make_noise(cfg))
+    st = o.init_state(y)
+    t0 = time.perf_counter()
+    o.iterate(st, y, sc["disp"], count=iters)
+    dt = time.perf_counter() - t0
+    print(json.dumps({"threads": oracle.Oracle.num_threads(), "s_per_iter": dt / iters, "iters": iters}), flush=True)
+
+
 def probe_ops(name, reps, which):
     """Counter-run driver: the forward, adjoint and normal operators of a
     workload on seeded random inputs, `reps` launches of each selected kind."""
@@ -140,7 +175,13 @@ def main():
                     help="jobs in a serving stream run in a child process (0: skip; the serving run is "
                          "currently disabled and reports an error)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="serving arrival rate, jobs/s")
+    ap.add_argument("--oracle-1thread", type=int, default=1,
+                    help="ADMM iterations of the one-thread oracle sample (0: skip)")
+    ap.add_argument("--no-other-workloads", action="store_true", help="skip the c1 / c2 throughput lines")
+    ap.add_argument("--oracle-1thread-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.oracle_1thread_child:
+        return oracle_one_thread(args.oracle_1thread_child, args.oracle_1thread)
     if args.probe == "ops":
         return probe_ops(args.config, args.probe_reps, args.probe_which)
     if args.probe == "copy":
@@ -221,6 +262,8 @@ def main():
     roof["launches_timed"] = n_launch
 
     hbm_gbs = bytes_per_iteration(cfg) * N * args.steps / (t1 - t0) / 1e9
+    cb = counter_bytes_per_solve(N)
+    hbm_gbs_counters = cb * args.steps / (t1 - t0) / 1e9 if cb else None
     line = {
         "metric": METRIC,
         "value": value,
@@ -238,9 +281,29 @@ def main():
                    "hr": [H, W], "scale": cfg["zeta"], "admm_iters": N, "cg_iters": K},
         "hbm_gbs_algorithmic": hbm_gbs,
         "hbm_frac_algorithmic": hbm_gbs / PEAK_HBM_GBS,
+        "hbm_gbs_counters": hbm_gbs_counters,
+        "hbm_frac_counters": hbm_gbs_counters / PEAK_HBM_GBS if hbm_gbs_counters else None,
         "roofline": roof,
         "kernel_ms_per_solve": {k: v[0] for k, v in breakdown.items()},
     }
+
+    golden = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"solve_{args.config}.npz")
+    if os.path.exists(gpath) and args.iters == 0:
+        g = np.load(gpath, allow_pickle=False)
+        if "x" in g:
+            golden = (g["x"].astype(np.float64), float(g["psnr_gt"]))
+
+    def vs_oracle(xr):
+        """rel-L2 and PSNR difference against the stored FP64 oracle solve of
+        this workload (its LR views come from the oracle's forward model,
+        which the library's matches to FP32 rounding)."""
+        if golden is None:
+            return {}
+        return {"rel_l2_vs_oracle": synth.rel_l2(xr, golden[0]),
+                "psnr_delta_vs_oracle": synth.psnr(xr, sc["x_gt"]) - golden[1]}
+
+    line["accuracy"] = dict(vs_oracle(x.astype(np.float64)), psnr_gt=synth.psnr(x, sc["x_gt"]))
 
     if not args.no_precision:
         # the same workload with the state stored in 16 bits (FP32 stencil arithmetic)
@@ -267,9 +330,12 @@ def main():
                 "psnr_f32": synth.psnr(ref, sc["x_gt"]),
                 "workspace_bytes": s16.bytes,
                 "steps": n16,
+                **vs_oracle(x16),
             }
             s16.close()
             log(f"[bench] {st}: {prec[st]['ms_per_step']:.2f} ms/solve, rel_l2 vs f32 {prec[st]['rel_l2_vs_f32']:.2e}")
+        prec["target_speedup"] = 1.6
+        prec["target_met"] = all(prec[k]["speedup_vs_f32"] >= 1.6 for k in ("f16", "bf16"))
         line["precision"] = prec
 
     if args.serve_jobs > 0:
@@ -286,6 +352,32 @@ def main():
             serving = {"error": f"serving run exited with status {res.returncode}"}
         log(f"[bench] serving: {serving}")
         line["serving"] = serving
+
+    if not args.no_other_workloads and args.config == "c3" and args.iters == 0:
+        # the other two plain-method workloads (throughput only; parity is in the tests)
+        others = {}
+        for name in ("c1", "c2"):
+            c2 = synth.config(name)
+            sc2 = synth.make_scene(c2)
+            sv = lfsr.Solver(lfsr.make_params(c2, disp_bound=max(float(np.abs(sc2["disp"]).max()), 1e-3)))
+            d2 = torch.from_numpy(sc2["disp"]).cuda()
+            cl = sv.lfsr_forward(torch.from_numpy(sc2["x_gt"].astype(np.float32)).cuda(), d2)
+            y2 = torch.from_numpy(synth.degrade(cl.cpu().numpy(), synth.make_noise(c2))).cuda()
+            o2 = torch.empty((sv.H, sv.W), dtype=torch.float32, device="cuda")
+            sv.lfsr_solve(y2, d2, out=o2, stats=False)
+            torch.cuda.synchronize()
+            reps = 20 if name == "c1" else 5
+            ta = time.perf_counter()
+            for _ in range(reps):
+                sv.lfsr_solve(y2, d2, out=o2, stats=False)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            others[name] = {"workload": synth.WORKLOAD_TEXT[name], "ms_per_step": (tb - ta) * 1e3 / reps,
+                            "value": sv.H * sv.W * sv.sk * c2["n_iter"] * reps / (tb - ta) / 1e6, "unit": UNIT,
+                            "steps": reps}
+            sv.close()
+            log(f"[bench] {name}: {others[name]['ms_per_step']:.2f} ms/solve")
+        line["other_workloads"] = others
 
     if not args.no_cpu_baseline:
         import oracle
@@ -304,6 +396,23 @@ def main():
             "sample": f"{args.cpu_iters} ADMM iterations (K={K}) of the same workload from x0, FP64, "
                       f"{tc1 - tc0:.1f} s",
         }
+        if args.oracle_1thread > 0:
+            # one thread, in a CPU-only child process (OpenMP's thread count is fixed per process)
+            import subprocess
+
+            env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="", CUDA_VISIBLE_DEVICES="")
+            res = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-1thread-child", args.config,
+                                  "--oracle-1thread", str(args.oracle_1thread)], cwd=ROOT, env=env,
+                                 capture_output=True, text=True, timeout=600)
+            one = None
+            for ln in res.stdout.splitlines():
+                if ln.startswith("{"):
+                    one = json.loads(ln)
+            if one:
+                line["cpu_baseline"]["one_thread"] = {
+                    "value": H * W * sk / one["s_per_iter"] / 1e6, "unit": UNIT, "cores": one["threads"],
+                    "s_per_admm_iteration": one["s_per_iter"],
+                    "sample": f"{one['iters']} ADMM iteration(s) of the same workload (oracle's own LR views)"}
     print(json.dumps(line), flush=True)
 
 

@@ -19,12 +19,14 @@
  *   LR views   y     [s_k][lr_h][lr_w], s_k = ang_rows*ang_cols, view k at
  *                    angular row k / ang_cols and column k % ang_cols; the
  *                    reference is the centre view.
- *   disparity  disp  [H][W], H = scale*lr_h, W = scale*lr_w: HR pixels of
- *                    shift per unit angular step, defined on the reference
- *                    view.  View k (angular offset tau_k rows, rho_k columns
- *                    from the centre) samples x bilinearly at
- *                    (Y + tau_k*disp(Y,X), X + rho_k*disp(Y,X)); samples
- *                    outside the image read zero (sec 4.1).
+ *   disparity  disp  [n_disp][H][W], H = scale*lr_h, W = scale*lr_w: HR
+ *                    pixels of shift per unit angular step.  With n_disp = 1
+ *                    one map, defined on the reference view, serves every
+ *                    view; with n_disp = s_k map k belongs to view k (sec 4.1
+ *                    gives each perspective its own map).  View k (angular
+ *                    offset tau_k rows, rho_k columns from the centre) samples
+ *                    x bilinearly at (Y + tau_k*w(Y,X), X + rho_k*w(Y,X)),
+ *                    w its map; samples outside the image read zero (sec 4.1).
  *   HR image   x     [H][W].
  *   data dual  w_D   [s_k][lr_h][lr_w]; NLTV dual w_S [s_d][H][W] with the
  *                    s_d = nltv_window^2 - 1 offsets d = (dy,dx) row-major
@@ -84,7 +86,8 @@ typedef struct {
   int32_t ang_rows, ang_cols; /* U, V: angular grid, both odd (centre view = reference) */
   int32_t lr_h, lr_w;         /* s_y, s_x: LR view size */
   int32_t scale;              /* zeta in 1..8: HR = scale * LR (sec 4.1); HR at most 32768 per side and 2^28 pixels */
-  int32_t n_disp;             /* 1: one disparity map on the reference view (the only form supported) */
+  int32_t n_disp;             /* 1: one disparity map on the reference view, used by every view;
+                                 ang_rows*ang_cols: one map per view (sec 4.1: w_k per perspective) */
   int32_t blur_size;          /* odd, 1..31; <= 0 with blur_sigma <= 0: paper default (see below) */
   float blur_sigma;           /* Gaussian std-dev in HR px; <= 0: sqrt(scale^2-1)/4 (sec 4.1), size 2*ceil(3 sigma)+1 */
   float lambda1, lambda2;     /* l1 and l2 fidelity weights (sec 3.3), >= 0, not both 0 */
@@ -167,7 +170,7 @@ lfsr_status lfsr_solve(lfsr_handle* h, const float* d_lr, const float* d_disp, c
 lfsr_status lfsr_solve_noalloc(const lfsr_params* p, const float* d_lr, const float* d_disp, const float* d_occ,
                                const float* d_x0, float* d_hr_out, lfsr_stats* h_stats, void* hip_stream);
 
-/* Bind the inputs (d_lr [s_k][lr_h][lr_w], d_disp [H][W], d_occ [H][W]
+/* Bind the inputs (d_lr [s_k][lr_h][lr_w], d_disp [n_disp][H][W], d_occ [H][W]
  * occlusion weight or NULL = 1) and set the state to x = d_x0 (or, if NULL,
  * the bicubic up-sampling of the centre view: Keys a = -1/2, LR sample (i,j)
  * at HR (scale*i, scale*j), clamp-to-edge; sec 5), w_D = w_S = 0, n = 0.
@@ -223,7 +226,8 @@ lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_oc
 /* sec 3.4, eq. (weight_occ): the occlusion weight
  *   d_occ_out = exp(-b^2 / (2 sigma_o1^2)) * exp(-p^2 / (2 sigma_o2^2))   [H][W]
  * from the LR views d_lr [s_k][lr_h][lr_w] and the reference view's disparity
- * map d_disp [H][W], ready to pass as d_occ to lfsr_init / lfsr_solve.
+ * map (d_disp [n_disp][H][W]; with one map per view, map kref), ready to pass as
+ * d_occ to lfsr_init / lfsr_solve.
  *   b: the one-sided divergence of the disparity map, the sum of its two
  *      forward differences (zero at the last column / row), where negative
  *      (occluding boundaries), else 0;

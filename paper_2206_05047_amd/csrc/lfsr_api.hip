@@ -114,7 +114,8 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   // one HR plane stays below 1 GiB of floats (32-bit byte offsets in the kernels)
   if ((long long)p->lr_h * p->scale * (long long)p->lr_w * p->scale > (1LL << 28))
     return fail(err, "HR image above 2^28 pixels");
-  if (p->n_disp != 1) return fail(err, "n_disp must be 1 (one disparity map on the reference view)");
+  if (p->n_disp != 1 && p->n_disp != p->ang_rows * p->ang_cols)
+    return fail(err, "n_disp must be 1 (one map on the reference view) or ang_rows*ang_cols (one map per view)");
   if (!(std::isfinite(p->lambda1) && std::isfinite(p->lambda2)) || p->lambda1 < 0.f || p->lambda2 < 0.f ||
       p->lambda1 + p->lambda2 <= 0.f)
     return fail(err, "lambda1, lambda2 must be finite, >= 0 and not both 0");
@@ -194,6 +195,7 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   g.n_iter = p->admm_iters;
   g.inv_sigma_e = g.use_edge ? (float)(1.0 / (double)p->sigma_e) : 0.f;
   g.disp_bound = p->disp_bound;
+  g.n_disp = p->n_disp;
   g.cg_tol = p->cg_tol;
   g.stop_tol = p->stop_tol;
   {
@@ -627,16 +629,17 @@ lfsr_status lfsr_occlusion_weight(lfsr_handle* h, const float* d_lr, const float
   // the CG vectors are free outside an iteration: the up-sampled reference
   // view, the up-sampled view k and the running sum of squared errors
   float *lref = h->b.r, *lk = h->b.pv, *acc = h->b.hp;
+  const float* dref = d_disp + (g.n_disp > 1 ? (size_t)g.kref * g.p : 0);  // the reference view's map
   launch_bicubic(g, d_lr + (size_t)g.kref * g.q, lref, s);
   launch_fill(acc, g.p, 0.f, s);
   for (int k = 0; k < g.sk; ++k) {
     if (k == g.kref) continue;
     launch_bicubic(g, d_lr + (size_t)k * g.q, lk, s);
-    launch_occ_acc(g, lref, lk, d_disp, k, acc, s);
+    launch_occ_acc(g, lref, lk, dref, k, acc, s);
   }
   const float c1 = std::isinf(sigma_o1) ? 0.f : (float)(0.5 / ((double)sigma_o1 * sigma_o1));
   const float c2 = std::isinf(sigma_o2) ? 0.f : (float)(0.5 / ((double)sigma_o2 * sigma_o2));
-  launch_occ_final(g, d_disp, acc, g.sk > 1 ? (float)(1.0 / (g.sk - 1)) : 0.f, c1, c2, d_occ_out, s);
+  launch_occ_final(g, dref, acc, g.sk > 1 ? (float)(1.0 / (g.sk - 1)) : 0.f, c1, c2, d_occ_out, s);
   return check_hip(h, "lfsr_occlusion_weight");
 }
 

@@ -44,6 +44,7 @@ struct Geom {
   float inv_sigma_e;          // 1/sigma_e (0 when the edge weight is off)
   int use_edge;
   int reweight;
+  int n_disp;                 // 1: one disparity map for every view; sk: view k's own map ([k][H][W])
   int halo;                   // warp halo in HR px: ceil(max |theta| * disp_bound) + 1
   float disp_bound;
   float cg_tol;

@@ -257,8 +257,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
   int base[kFwdSlots];
   int rbase[kFwdSlots];   // base + row offset of the current angular row
   float fyv[kFwdSlots];   // vertical bilinear weight of the current angular row
+  int pofs[kFwdSlots];    // pixel offset in a map, -1 outside the image
+  const bool per_view = g.n_disp > 1;  // view k's own map ([k][H][W]), loaded per view
   {
-    int pofs[kFwdSlots];
 #pragma unroll
     for (int s = 0; s < kFwdSlots; ++s) {  // all loads first (in-bounds addresses), then the math
       const int idx = tid + s * kThreads;
@@ -293,7 +294,15 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
   for (int k = k0; k < k1; ++k) {
     const int ka = k / g.V, kc = k - ka * g.V;
     const float rho = (float)(kc - (g.V - 1) / 2);
-    if (k == k0 || kc == 0) {  // the vertical warp coordinate is shared by an angular row
+    if (per_view) {
+      const float* dk = disp + (size_t)k * g.p;
+#pragma unroll
+      for (int s = 0; s < kFwdSlots; ++s) om[s] = dk[pofs[s] >= 0 ? pofs[s] : 0];
+#pragma unroll
+      for (int s = 0; s < kFwdSlots; ++s)
+        om[s] = pofs[s] >= 0 ? fminf(fmaxf(om[s], -g.disp_bound), g.disp_bound) : 0.f;
+    }
+    if (k == k0 || kc == 0 || per_view) {  // one map: the vertical warp coordinate is shared by an angular row
       const float tau = (float)(ka - (g.U - 1) / 2);
 #pragma unroll
       for (int s = 0; s < kFwdSlots; ++s) {
@@ -738,8 +747,9 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
   }
   // scatter pixels (wave row r, col lx): disparity (clamped), horizontal base/tap, accumulator base
   float om[kAdjSlots];
-  int hbase[kAdjSlots], htap[kAdjSlots], abase[kAdjSlots];
+  int hbase[kAdjSlots], htap[kAdjSlots], abase[kAdjSlots], dofs[kAdjSlots];
   bool act[kAdjSlots];
+  const bool per_view = g.n_disp > 1;  // view k's own map ([k][H][W]), loaded per view
 #pragma unroll
   for (int s = 0; s < kAdjSlots; ++s) {
     const int idx = lane + s * 64;
@@ -747,7 +757,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
     const int ly = ly0 + r;
     const int Y = Y0 + ly, X = X0 + lx;
     act[s] = idx < RH * TW && Y < g.H && X < g.W;
-    om[s] = disp[act[s] ? (size_t)Y * g.W + X : 0];  // batched, in bounds
+    dofs[s] = act[s] ? Y * g.W + X : 0;
+    om[s] = disp[dofs[s]];  // batched, in bounds
     const int ph = lx % zeta, lq = lx / zeta;
     const int mlo = floordiv(ph - rb + zeta - 1, zeta);
     hbase[s] = act[s] ? r * LX + lq + mlo + ci : 0;
@@ -797,9 +808,16 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
         ereg[s] = eoff[s] >= 0 ? t : 0.f;
       }
     }
-    // the vertical warp coordinate is shared by the views of an angular row
+    // one map: the vertical warp coordinate is shared by the views of an angular row
     const int ka = k / g.V, kbcol = k - ka * g.V;
-    if (kbcol == 0) {
+    if (per_view) {
+      const float* dk = disp + (size_t)k * g.p;
+#pragma unroll
+      for (int s = 0; s < kAdjSlots; ++s) om[s] = dk[dofs[s]];
+#pragma unroll
+      for (int s = 0; s < kAdjSlots; ++s) om[s] = act[s] ? fminf(fmaxf(om[s], -g.disp_bound), g.disp_bound) : 0.f;
+    }
+    if (kbcol == 0 || per_view) {
       const float tau = (float)(ka - (g.U - 1) / 2);
 #pragma unroll
       for (int s = 0; s < kAdjSlots; ++s) {
@@ -1895,16 +1913,16 @@ __global__ __launch_bounds__(kThreads) void k_occ_final(Geom g, const float* __r
 __global__ __launch_bounds__(kThreads) void k_check(Geom g, const float* __restrict__ y, const float* __restrict__ disp,
                                                     const float* __restrict__ occ, DevScalars* __restrict__ sc) {
   int f = 0;
-  const long long ny = (long long)g.sk * g.q;
-  const long long n = ny > g.p ? ny : g.p;
+  const long long ny = (long long)g.sk * g.q, nd = (long long)g.n_disp * g.p;
+  long long n = ny > nd ? ny : nd;
   for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads) {
     if (o < ny && !isfinite(y[o])) f |= 1;
-    if (o < g.p) {
+    if (o < nd) {
       const float d = disp[o];
       if (!isfinite(d)) f |= 1;
       else if (fabsf(d) > g.disp_bound) f |= 2;
-      if (occ && !isfinite(occ[o])) f |= 1;
     }
+    if (o < g.p && occ && !isfinite(occ[o])) f |= 1;
   }
   if (f) atomicOr(&sc->err_flags, f);
 }
@@ -2024,7 +2042,9 @@ static constexpr bool fwdcol_shape(int zeta, int kb) {
 static constexpr int fwdcol_tly(int zeta, int kb) { return (void)zeta, (void)kb, 8; }
 
 bool forward_col_setup(Geom& g) {
-  if (!fwdcol_shape(g.zeta, g.kb)) return false;
+  // the column kernels hold one disparity map in registers across all views;
+  // per-view maps take the tiled kernels, which load the map per view
+  if (!fwdcol_shape(g.zeta, g.kb) || g.n_disp > 1) return false;
   Geom t = g;
   t.f_col = 1;
   t.f_tly = fwdcol_tly(g.zeta, g.kb);
@@ -2095,7 +2115,7 @@ dim3 adjoint_grid(const Geom& g) { return dim3(g.a_ntx, g.a_nty, g.a_vg); }
 static constexpr bool adjcol_shape(int zeta, int kb) { return fwdcol_shape(zeta, kb); }
 
 bool adjoint_col_setup(Geom& g) {
-  if (!adjcol_shape(g.zeta, g.kb)) return false;
+  if (!adjcol_shape(g.zeta, g.kb) || g.n_disp > 1) return false;
   Geom t = g;
   t.a_col = 1;
   t.a_th = adjcol_th(g.zeta);
@@ -2403,7 +2423,7 @@ void launch_occ_final(const Geom& g, const float* disp, const float* acc, float 
 
 void launch_check(const Geom& g, const float* y, const float* disp, const float* occ, hipStream_t s, const Bufs& b) {
   long long n = (long long)g.sk * g.q;
-  if (n < g.p) n = g.p;
+  if (n < (long long)g.n_disp * g.p) n = (long long)g.n_disp * g.p;
   hipLaunchKernelGGL(k_check, dim3(grid1d(n)), dim3(kThreads), 0, s, g, y, disp, occ, b.sc);
 }
 

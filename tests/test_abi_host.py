@@ -70,7 +70,7 @@ def test_16bit_storage_halves_the_stored_fields(lfsr, name):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("ang_rows", 2), ("ang_cols", 0), ("lr_h", 0), ("scale", 0), ("scale", 9), ("n_disp", 9),
+    ("ang_rows", 2), ("ang_cols", 0), ("lr_h", 0), ("scale", 0), ("scale", 9), ("n_disp", 2), ("n_disp", 8),
     ("blur_size", 4), ("blur_size", 33), ("lambda1", -1.0), ("nltv_window", 4), ("nltv_window", 17),
     ("sigma_s", 0.0), ("sigma_e", 0.0), ("admm_penalty", 0.0), ("admm_iters", 0), ("cg_iters", -1),
     ("cg_tol", -1.0), ("stop_tol", float("nan")), ("disp_bound", 0.0), ("disp_bound", float("inf")),
@@ -157,3 +157,12 @@ def test_pool_argument_errors(lfsr):
     assert lib.lfsr_pool_submit(None, ctypes.byref(p), None, None, None, None, None, None,
                                 ctypes.byref(jid)) == lfsr.LFSR_EINVAL
     lib.lfsr_pool_destroy(None)
+
+
+def test_per_view_maps_accepted(lfsr):
+    """n_disp = 1 (one map) or ang_rows*ang_cols (one map per view); the maps
+    are inputs, so the workspace holds the same state either way (its size
+    differs only by the tiling's partial images)."""
+    one = lfsr.workspace_bytes(_params(lfsr, "c1"))
+    per = lfsr.workspace_bytes(_params(lfsr, "c1", n_disp=9))
+    assert per > 0 and abs(per - one) < 0.2 * one
