@@ -44,6 +44,7 @@ class OrcParams(ctypes.Structure):
         ("theta", ctypes.c_double),
         ("cg_iter", ctypes.c_int32),
         ("cg_tol", ctypes.c_double),
+        ("weight_kind", ctypes.c_int32),
     ]
 
 
@@ -66,6 +67,7 @@ def _load():
     I = ctypes.c_int
     sigs = {
         "orc_num_threads": ([], I),
+        "orc_ref_view": ([P], I),
         "orc_blur_kernel": ([P, D], None),
         "orc_warp": ([P, D, D, I, D], None),
         "orc_warp_t_acc": ([P, D, D, I, D], None),
@@ -121,6 +123,7 @@ class Problem:
     cg_tol: float = 0.0
     reweight: int = 1
     n_disp: int = 1
+    weight_kind: int = 0
 
     @classmethod
     def from_any(cls, cfg) -> "Problem":
@@ -156,7 +159,7 @@ class Problem:
             self.U, self.V, self.sy, self.sx, self.zeta, self.n_disp, self.kb, float(self.sigma_b),
             float(self.lambda1), float(self.lambda2), self.win, float(self.sigma_s),
             float(self.sigma_e), int(self.reweight), float(self.theta), self.cg_iter,
-            float(self.cg_tol),
+            float(self.cg_tol), int(self.weight_kind),
         )
 
 
@@ -302,10 +305,13 @@ class Oracle:
         return out
 
     def x0(self, y):
-        """Bicubic up-sampling of the centre (reference) view."""
+        """Bicubic up-sampling of the reference view."""
         y = _f64(y, self.lr_shape)
-        kref = (self.pb.U // 2) * self.pb.V + self.pb.V // 2
-        return self.bicubic(y[kref])
+        return self.bicubic(y[self.ref_view()])
+
+    def ref_view(self):
+        """Index of the reference view (angular offset (0, 0))."""
+        return self.lib.orc_ref_view(self._pp)
 
     def normal_apply(self, disp, m, x):
         x = _f64(x, self.hr_shape)

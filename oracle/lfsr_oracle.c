@@ -59,6 +59,7 @@ typedef struct {
   double theta;          /* ADMM penalty (vartheta) */
   int32_t cg_iter;       /* K */
   double cg_tol;         /* tau */
+  int32_t weight_kind;   /* spatial weight: 0 exp(-|d|^2/sigma_s); 1 BTV sigma_s^(|dy|+|dx|) */
 } orc_params;
 
 /* ------------------------------------------------------------------ sizes */
@@ -78,12 +79,18 @@ int orc_num_threads(void) {
 #endif
 }
 
-/* Angular offset of view k from the centre view (sec 3.1: the SAIs are a
- * 1-D set of s_k observations taken from the 2-D angular grid). */
+/* Angular offset of view k from the reference view (sec 3.1: the SAIs are a
+ * 1-D set of s_k observations taken from the 2-D angular grid).  The
+ * reference is the centre view of an odd grid; an even grid (the multi-image
+ * workload: 2 x 2 images) takes offsets 0 .. U-1 - (U-1)/2 from view
+ * ((U-1)/2, (V-1)/2). */
 void orc_view_offset(const orc_params* p, int k, int* tau, int* rho) {
   *tau = k / p->V - (p->U - 1) / 2;
   *rho = k % p->V - (p->V - 1) / 2;
 }
+
+/* The reference view: the one with angular offset (0, 0). */
+int orc_ref_view(const orc_params* p) { return ((p->U - 1) / 2) * p->V + (p->V - 1) / 2; }
 
 static const double* disp_of(const orc_params* p, const double* disp, int k) {
   return p->n_disp == 1 ? disp : disp + (int64_t)k * n_hr(p);
@@ -296,8 +303,11 @@ void orc_adjoint(const orc_params* p, const double* e, const double* disp, doubl
 
 /* ------------------------------------------------------------ weights */
 
-/* sec 3.4: spatial weight of offset d (read with a decreasing exponent). */
+/* sec 3.4: spatial weight of offset d (read with a decreasing exponent); or,
+ * for the BTV regulariser the paper matches in its multi-image experiment
+ * (sec 7.3), alpha^(|dy|+|dx|) with alpha = sigma_s in (0, 1]. */
 double orc_spatial_weight(const orc_params* p, int dy, int dx) {
+  if (p->weight_kind == 1) return pow(p->sigma_s, (double)(abs(dy) + abs(dx)));
   return exp(-(double)(dy * dy + dx * dx) / p->sigma_s);
 }
 
@@ -433,7 +443,7 @@ void orc_bicubic(const orc_params* p, const double* lr, double* out) {
 void orc_occlusion_weight(const orc_params* p, const double* y, const double* disp, double s1, double s2,
                           double* out) {
   const int64_t H = hr_h(p), W = hr_w(p), n = n_hr(p), q = n_lr(p);
-  const int sk = n_views(p), kref = (p->U / 2) * p->V + p->V / 2;
+  const int sk = n_views(p), kref = orc_ref_view(p);
   const double* w = disp_of(p, disp, kref);
   double* l0 = (double*)malloc(sizeof(double) * n);
   double* li = (double*)malloc(sizeof(double) * n);

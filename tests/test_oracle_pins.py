@@ -638,3 +638,58 @@ def test_occlusion_weight_sampling_equals_scipy_map_coordinates():
     s2 = 0.2
     got = o.occlusion_weight(y, d, np.inf, s2)
     np.testing.assert_allclose(got, np.exp(-p2 / (2 * s2 ** 2)), rtol=1e-11, atol=1e-14)
+
+
+# ---------------------------------------------------------------- multi-image workload (sec 7.3)
+
+def test_btv_spatial_weight_closed_form():
+    """BTV weights (sec 7.3 configures the non-local weights to match BTV):
+    alpha^(|dy|+|dx|) with alpha = sigma_s; the Gaussian form otherwise."""
+    o = _o(win=5, sigma_s=0.7, weight_kind=1)
+    for dy, dx in [(0, 1), (-1, 0), (1, 1), (-2, 1), (2, -2)]:
+        assert abs(o.spatial_weight(dy, dx) - 0.7 ** (abs(dy) + abs(dx))) < 1e-15
+    g = _o(win=5, sigma_s=0.7)
+    assert abs(g.spatial_weight(1, 1) - np.exp(-2 / 0.7)) < 1e-15
+
+
+def test_btv_regulariser_is_twice_the_half_window_pair_sum():
+    """With m = 1 (no edge weight) and BTV weights, the full-window NLTV term
+    sum_d sum_z c_d |x(z) - x(z+d)| counts every unordered pixel pair twice
+    (c_d = c_-d): it equals 2 x the half-window form of BTV (offsets with
+    dy > 0, or dy = 0 and dx > 0), brute-forced here over pixel pairs."""
+    o = _o(win=5, sigma_s=0.6, weight_kind=1, sigma_e=np.inf, zeta=1, sy=9, sx=8)
+    x = _rng(61).uniform(0, 1, o.hr_shape)
+    m = np.ones(o.hr_shape)
+    full = np.abs(o.nltv_grad(x, m)).sum()
+    H, W = o.hr_shape
+    half = 0.0
+    for dy in range(0, 3):
+        for dx in range(-2, 3):
+            if dy == 0 and dx <= 0:
+                continue
+            c = 0.6 ** (abs(dy) + abs(dx))
+            for Y in range(H):
+                for X in range(W):
+                    if 0 <= Y + dy < H and 0 <= X + dx < W:
+                        half += c * abs(x[Y, X] - x[Y + dy, X + dx])
+    assert abs(full - 2 * half) < 1e-12 * full
+
+
+def test_even_grid_offsets_and_reference_view():
+    """A 2 x 2 set of images (the x2 multi-image workload): offsets {0,1}^2
+    from view 0, which is the reference (x0 is its bicubic up-sampling); with
+    a constant map of 1/2 the views are the reference shifted by half a pixel
+    (the warp against scipy's linear interpolation)."""
+    o = _o(U=2, V=2, zeta=1, sy=10, sx=11)
+    assert [o.view_offset(k) for k in range(4)] == [(0, 0), (0, 1), (1, 0), (1, 1)]
+    assert o.ref_view() == 0
+    y = _rng(62).uniform(0, 1, o.lr_shape)
+    np.testing.assert_array_equal(o.x0(y), o.bicubic(y[0]))
+    x = _rng(63).uniform(0, 1, o.hr_shape)
+    H, W = o.hr_shape
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    for k in range(4):
+        tau, rho = o.view_offset(k)
+        ref = ndimage.map_coordinates(x, [yy + 0.5 * tau, xx + 0.5 * rho], order=1, mode="grid-constant", cval=0.0)
+        np.testing.assert_allclose(o.warp(x, np.full((H, W), 0.5), k), ref, rtol=0, atol=1e-14)
+    assert _o(U=3, V=5).ref_view() == 7
