@@ -366,6 +366,60 @@ class Oracle:
         stats = self.iterate(st, y, disp, occ, count=n)
         return st["x"], stats
 
+    # -- gradient descent baselines (sec 7.1: gd and gd-ls against ADMM)
+    def cost_parts(self, y, disp, m, x):
+        """J(x) (sec 4, cost J), and the two factors of a subgradient: q =
+        lambda1 sgn(r) + 2 lambda2 r on the LR views (r = A x - y) and
+        S^T sgn(V (I - S) x) on the HR grid (sgn(0) = 0)."""
+        pb = self.pb
+        r = self.forward(x, disp) - _f64(y, self.lr_shape)
+        g = self.nltv_grad(x, m)
+        J = pb.lambda1 * np.abs(r).sum() + pb.lambda2 * (r * r).sum() + np.abs(g).sum()
+        q = pb.lambda1 * np.sign(r) + 2.0 * pb.lambda2 * r
+        t = self.nltv_div(np.sign(g), m) if pb.sd > 0 else np.zeros(self.hr_shape)
+        return J, q, t
+
+    def gd(self, y, disp, iters, step, line_search=False, x0=None, occ=None):
+        """Subgradient descent on J with the weights fixed at m = w_e(x0) w_o
+        (the comparison of sec 7.1).  Each step costs computation units (CU)
+        as the paper counts them: one CU is A with S (the cost), or A^T with
+        S^T (the gradient).  Fixed step (gd): x <- x - step g, 2 CU.  With
+        line search (gd-ls): backtracking from twice the last accepted step
+        (the first from `step`), halving until the Armijo condition
+        J(x - eta g) <= J(x) - 1e-4 eta |g|^2 holds (one CU per trial, at most
+        30 trials, else the step is skipped), then A^T for the new gradient.
+        Returns (x, hist) with hist[n] = (J(x_n), CU spent after step n,
+        eta) for n = 0 (x0) .. iters."""
+        x = self.x0(y) if x0 is None else _f64(x0, self.hr_shape).copy()
+        m = self.edge_weight(x, occ)
+        J, q, t = self.cost_parts(y, disp, m, x)
+        g = self.adjoint(q, disp) + t
+        cu = 2
+        hist = [(J, cu, 0.0)]
+        eta = step
+        for _ in range(iters):
+            if not line_search:
+                x = x - step * g
+                J, q, t = self.cost_parts(y, disp, m, x)
+                g = self.adjoint(q, disp) + t
+                cu += 2
+                hist.append((J, cu, step))
+                continue
+            gg = float((g * g).sum())
+            eta = 2.0 * eta if len(hist) > 1 else step
+            for _trial in range(30):
+                xc = x - eta * g
+                Jc, qc, tc = self.cost_parts(y, disp, m, xc)
+                cu += 1
+                if Jc <= J - 1e-4 * eta * gg:
+                    x, J, q, t = xc, Jc, qc, tc
+                    g = self.adjoint(q, disp) + t
+                    cu += 1
+                    break
+                eta *= 0.5
+            hist.append((J, cu, eta))
+        return x, np.array(hist)
+
     def soft(self, u, t):
         return self.lib.orc_soft_threshold(float(u), float(t))
 

@@ -693,3 +693,55 @@ def test_even_grid_offsets_and_reference_view():
         ref = ndimage.map_coordinates(x, [yy + 0.5 * tau, xx + 0.5 * rho], order=1, mode="grid-constant", cval=0.0)
         np.testing.assert_allclose(o.warp(x, np.full((H, W), 0.5), k), ref, rtol=0, atol=1e-14)
     assert _o(U=3, V=5).ref_view() == 7
+
+
+# ---------------------------------------------------------------- gradient-descent baselines (sec 7.1)
+
+def test_cost_subgradient_matches_finite_differences():
+    """At a generic point (no residual or pixel difference at zero) J is
+    differentiable and the subgradient A^T q + S^T sgn(g) is its gradient:
+    central differences along random directions agree.  Fails for a dropped
+    factor 2 on the l2 part, a sign error or a transposed operator."""
+    o = _o(win=3, sigma_e=np.inf, reweight=0)
+    rng = _rng(81)
+    d = _disp_smooth(o, rng)
+    y = rng.uniform(0, 1, o.lr_shape)
+    x = rng.uniform(0, 1, o.hr_shape)
+    m = rng.uniform(0.3, 1.0, o.hr_shape)
+    J, q, t = o.cost_parts(y, d, m, x)
+    assert abs(J - o.objective(y, d, m, x)) < 1e-10 * J
+    grad = o.adjoint(q, d) + t
+    for _ in range(4):
+        v = rng.standard_normal(o.hr_shape)
+        eps = 1e-6
+        fd = (o.cost_parts(y, d, m, x + eps * v)[0] - o.cost_parts(y, d, m, x - eps * v)[0]) / (2 * eps)
+        assert abs(fd - np.vdot(grad, v)) < 1e-6 * abs(fd)
+
+
+def test_gd_l2_only_equals_dense_iteration():
+    """lambda1 = 0 and no regulariser: gd is x <- x - step 2 lambda2 A^T (A x - y),
+    reproduced with a dense matrix of A built column by column from the
+    forward operator alone."""
+    o = _o(sy=4, sx=5, lambda1=0.0, lambda2=1.5, win=1, sigma_e=np.inf, reweight=0)
+    rng = _rng(82)
+    d = _disp_smooth(o, rng)
+    y = rng.uniform(0, 1, o.lr_shape)
+    n = o.hr_shape[0] * o.hr_shape[1]
+    A = np.stack([o.forward(np.eye(n)[i].reshape(o.hr_shape), d).ravel() for i in range(n)], axis=1)
+    x, hist = o.gd(y, d, 5, 0.05)
+    xr = o.x0(y).ravel()
+    for _ in range(5):
+        xr = xr - 0.05 * 2 * 1.5 * A.T @ (A @ xr - y.ravel())
+    np.testing.assert_allclose(x.ravel(), xr, rtol=0, atol=1e-12)
+    assert list(hist[:, 1]) == [2, 4, 6, 8, 10, 12]
+
+
+def test_gd_line_search_is_monotone_with_armijo_steps():
+    o = _o(reweight=0)
+    rng = _rng(83)
+    d = _disp_smooth(o, rng)
+    y = rng.uniform(0, 1, o.lr_shape)
+    x, hist = o.gd(y, d, 12, 0.05, line_search=True)
+    J, cu = hist[:, 0], hist[:, 1]
+    assert np.all(np.diff(J) <= 0) and J[-1] < J[0]
+    assert np.all(np.diff(cu) >= 2)  # at least one trial and one adjoint per step
