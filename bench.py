@@ -111,6 +111,70 @@ def oracle_one_thread(name, iters):
     print(json.dumps({"threads": oracle.Oracle.num_threads(), "s_per_iter": dt / iters, "iters": iters}), flush=True)
 
 
+def convergence(name, budget):
+    """Loss against computation units (CU) for the four solvers the paper
+    compares (sec 7.1) on one workload with the weights fixed at x0: gd (fixed
+    step, the best of a small sweep at 80 CU), gd-ls (backtracking), admm-5
+    and admm-10 (K = 5 / 10 CG steps, early stop at |r|^2 <= tau).  A CU is A
+    with S (a cost) or A^T with S^T (a gradient); an ADMM iteration costs
+    2 + 2 K_n (K_n CG steps taken).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2206_05047_amd import lfsr, synth
+
+    torch.cuda.set_device(0)
+    cfg = synth.config(name, reweight=0)
+    sc = synth.make_scene(cfg)
+    bound = max(float(np.abs(sc["disp"]).max()), 1e-3)
+    disp = torch.from_numpy(sc["disp"]).cuda()
+    base = lfsr.Solver(lfsr.make_params(cfg, disp_bound=bound))
+    clean = base.lfsr_forward(torch.from_numpy(sc["x_gt"].astype(np.float32)).cuda(), disp)
+    y = torch.from_numpy(synth.degrade(clean.cpu().numpy(), synth.make_noise(cfg))).cuda()
+    curves, info = {}, {}
+
+    def run_gd(step, ls, iters):
+        base.lfsr_init(y, disp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = base.lfsr_gd(iters, step, line_search=ls)
+        dt = time.perf_counter() - t0
+        return h, dt
+
+    sweep = {}
+    for step in (5e-4, 1e-3, 2e-3, 4e-3, 8e-3):
+        h, _ = run_gd(step, False, 39)
+        sweep[step] = float(h[-1, 0])
+    best = min(sweep, key=sweep.get)
+    h, dt = run_gd(best, False, budget // 2 - 1)
+    curves["gd"] = [(float(c), float(j)) for j, c, _ in h]
+    info["gd"] = {"step": best, "sweep_J_at_80cu": sweep, "ms_per_cu": dt * 1e3 / h[-1, 1]}
+    h, dt = run_gd(10 * best, True, budget)
+    keep = h[:, 1] <= budget
+    curves["gd-ls"] = [(float(c), float(j)) for j, c, _ in h[keep]]
+    info["gd-ls"] = {"first_step": 10 * best, "ms_per_cu": dt * 1e3 / h[-1, 1]}
+    for K in (5, 10):
+        tau = 1.0
+        s = lfsr.Solver(lfsr.make_params(dict(cfg, cg_iter=K, cg_tol=tau, n_iter=budget // 4), disp_bound=bound))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = s.lfsr_solve(y, disp)
+        dt = time.perf_counter() - t0
+        hist = st["hist"]
+        cu_before = np.concatenate([[0.0], np.cumsum(2 + 2 * hist[:, 3])])
+        # J_n is the cost at x^(n-1), evaluated by the first CU of iteration n
+        pts = [(float(cu_before[n] + 1), float(hist[n, 0])) for n in range(len(hist)) if cu_before[n] + 1 <= budget]
+        curves[f"admm-{K}"] = pts
+        info[f"admm-{K}"] = {"cg_tol": tau, "cg_steps": [int(k) for k in hist[:, 3]],
+                             "ms_per_cu": dt * 1e3 / cu_before[-1]}
+        s.close()
+    marks = [20, 40, 80, 160, 320, budget]
+    table = {k: {m: min([j for c, j in v if c <= m], default=None) for m in marks} for k, v in curves.items()}
+    print(json.dumps({"experiment": "loss vs computation units", "workload": synth.WORKLOAD_TEXT.get(name, name),
+                      "weights": "fixed at x0 (reweight = 0)", "budget_cu": budget, "best_J_within_cu": table,
+                      "info": info, "curves": curves}), flush=True)
+
+
 def probe_ops(name, reps, which):
     """Counter-run driver: the forward, adjoint and normal operators of a
     workload on seeded random inputs, `reps` launches of each selected kind."""
@@ -179,7 +243,12 @@ def main():
                     help="ADMM iterations of the one-thread oracle sample (0: skip)")
     ap.add_argument("--no-other-workloads", action="store_true", help="skip the c1 / c2 throughput lines")
     ap.add_argument("--oracle-1thread-child", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--convergence", default=None, metavar="WORKLOAD",
+                    help="instead of the benchmark: loss vs computation units of gd, gd-ls, admm-5, admm-10")
+    ap.add_argument("--budget", type=int, default=400, help="computation units of the convergence experiment")
     args = ap.parse_args()
+    if args.convergence:
+        return convergence(args.convergence, args.budget)
     if args.oracle_1thread_child:
         return oracle_one_thread(args.oracle_1thread_child, args.oracle_1thread)
     if args.probe == "ops":
@@ -354,9 +423,10 @@ def main():
         line["serving"] = serving
 
     if not args.no_other_workloads and args.config == "c3" and args.iters == 0:
-        # the other two plain-method workloads (throughput only; parity is in the tests)
+        # the other two plain-method workloads and the multi-image workload at 5760^2
+        # (throughput only; parity is in the tests)
         others = {}
-        for name in ("c1", "c2"):
+        for name in ("c1", "c2", "misr2", "misr3"):
             c2 = synth.config(name)
             sc2 = synth.make_scene(c2)
             sv = lfsr.Solver(lfsr.make_params(c2, disp_bound=max(float(np.abs(sc2["disp"]).max()), 1e-3)))
@@ -366,7 +436,7 @@ def main():
             o2 = torch.empty((sv.H, sv.W), dtype=torch.float32, device="cuda")
             sv.lfsr_solve(y2, d2, out=o2, stats=False)
             torch.cuda.synchronize()
-            reps = 20 if name == "c1" else 5
+            reps = {"c1": 20, "c2": 5}.get(name, 2)
             ta = time.perf_counter()
             for _ in range(reps):
                 sv.lfsr_solve(y2, d2, out=o2, stats=False)

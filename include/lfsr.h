@@ -17,8 +17,10 @@
  *
  * Layouts (all row-major, no padding, float32 unless stated):
  *   LR views   y     [s_k][lr_h][lr_w], s_k = ang_rows*ang_cols, view k at
- *                    angular row k / ang_cols and column k % ang_cols; the
- *                    reference is the centre view.
+ *                    angular row k / ang_cols and column k % ang_cols, angular
+ *                    offset tau_k = k / ang_cols - (ang_rows-1)/2 rows and
+ *                    rho_k = k % ang_cols - (ang_cols-1)/2 columns; the
+ *                    reference is the view with offset (0, 0).
  *   disparity  disp  [n_disp][H][W], H = scale*lr_h, W = scale*lr_w: HR
  *                    pixels of shift per unit angular step.  With n_disp = 1
  *                    one map, defined on the reference view, serves every
@@ -83,7 +85,9 @@ typedef enum {
 typedef enum { LFSR_F32 = 0, LFSR_F16 = 1, LFSR_BF16 = 2 } lfsr_storage;
 
 typedef struct {
-  int32_t ang_rows, ang_cols; /* U, V: angular grid, both odd (centre view = reference) */
+  int32_t ang_rows, ang_cols; /* U, V: angular grid; the reference is view ((U-1)/2, (V-1)/2), the
+                                 centre of an odd grid (an even grid, e.g. the 2 x 2 images of the
+                                 multi-image workload, has offsets 0 .. U/2 from it) */
   int32_t lr_h, lr_w;         /* s_y, s_x: LR view size */
   int32_t scale;              /* zeta in 1..8: HR = scale * LR (sec 4.1); HR at most 32768 per side and 2^28 pixels */
   int32_t n_disp;             /* 1: one disparity map on the reference view, used by every view;
@@ -102,6 +106,8 @@ typedef struct {
   float stop_tol;             /* >= 0: stop after iteration n once res_n <= stop_tol * res_1 (0: run N) */
   float disp_bound;           /* > 0: the caller's bound on |disp| (sizes the warp halo; larger values are an input error) */
   int32_t storage;            /* lfsr_storage of the solver state (see below) */
+  int32_t spatial_weight;     /* NLTV spatial weight of offset d: 0 = exp(-|d|^2 / sigma_s) (sec 3.4);
+                                 1 = BTV, sigma_s^(|dy|+|dx|) with 0 < sigma_s <= 1 (sec 7.3) */
 } lfsr_params;
 
 #define LFSR_NSTAT 6
@@ -240,6 +246,25 @@ lfsr_status lfsr_edge_weight(lfsr_handle* h, const float* d_x, const float* d_oc
  * work buffers (must not overlap an iteration); FP32. */
 lfsr_status lfsr_occlusion_weight(lfsr_handle* h, const float* d_lr, const float* d_disp, float sigma_o1,
                                   float sigma_o2, float* d_occ_out, void* hip_stream);
+
+/* The gradient-descent baselines the paper compares ADMM with (sec 7.1: gd
+ * and gd-ls): subgradient descent on the cost J of sec 4 with the weights
+ * fixed at the starting point (m = w_e(x) * occ), from the state lfsr_init
+ * (or lfsr_write_state) left, updating the handle's x in place (read it with
+ * lfsr_read_state).  The subgradient is
+ *   sum_k A_k^T (lambda1 sgn(r_k) + 2 lambda2 r_k) + S^T sgn(V (I - S) x),
+ * r_k = A_k x - y_k, sgn(0) = 0.  line_search = 0: x <- x - step g, each step
+ * two computation units (CU: one is A with S for a cost, one A^T with S^T
+ * for a gradient).  line_search = 1: backtracking from twice the last
+ * accepted step (the first from `step`), halving until
+ * J(x - eta g) <= J(x) - 1e-4 eta |g|^2 (one CU per trial, at most 30; a step
+ * with no accepted trial leaves x unchanged), then one CU for the gradient
+ * at the new point.  h_hist (NULL or [iters + 1][3] doubles) receives
+ * (J(x_n), CU spent after step n, eta) for n = 0 .. iters.  FP32 storage
+ * only (LFSR_EINVAL otherwise).  Synchronises the stream after every cost
+ * evaluation; uses the handle's work buffers. */
+lfsr_status lfsr_gd(lfsr_handle* h, int32_t iters, float step, int32_t line_search, double* h_hist,
+                    void* hip_stream);
 
 /* sec 5: bicubic up-sampling of one LR view d_lr_view [lr_h][lr_w] to [H][W]
  * (the x0 of lfsr_init). */

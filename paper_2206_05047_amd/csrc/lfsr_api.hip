@@ -106,7 +106,6 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   Geom& g = pl->g;
   if (p->ang_rows < 1 || p->ang_cols < 1 || p->ang_rows > 63 || p->ang_cols > 63)
     return fail(err, "ang_rows/ang_cols must be in 1..63");
-  if (p->ang_rows % 2 == 0 || p->ang_cols % 2 == 0) return fail(err, "ang_rows/ang_cols must be odd (centre view)");
   if (p->lr_h < 1 || p->lr_w < 1) return fail(err, "lr_h/lr_w must be >= 1");
   if (p->scale < 1 || p->scale > 8) return fail(err, "scale must be in 1..8");
   if ((long long)p->lr_h * p->scale > 32768 || (long long)p->lr_w * p->scale > 32768)
@@ -133,11 +132,13 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   if (p->reweight != 0 && p->reweight != 1) return fail(err, "reweight must be 0 or 1");
   if (p->storage != LFSR_F32 && p->storage != LFSR_F16 && p->storage != LFSR_BF16)
     return fail(err, "storage must be LFSR_F32, LFSR_F16 or LFSR_BF16");
+  if (p->spatial_weight != 0 && p->spatial_weight != 1) return fail(err, "spatial_weight must be 0 or 1");
+  if (p->spatial_weight == 1 && !(p->sigma_s <= 1.f)) return fail(err, "BTV spatial weight needs 0 < sigma_s <= 1");
 
   g.U = p->ang_rows;
   g.V = p->ang_cols;
   g.sk = g.U * g.V;
-  g.kref = (g.U / 2) * g.V + g.V / 2;
+  g.kref = ((g.U - 1) / 2) * g.V + (g.V - 1) / 2;  // the view with angular offset (0, 0)
   g.sy = p->lr_h;
   g.sx = p->lr_w;
   g.zeta = p->scale;
@@ -178,7 +179,8 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
     for (int d = 0; d < g.sd; ++d) {
       const int id = d < half ? d : d + 1;
       const int dy = id / g.win - g.rw, dx = id % g.win - g.rw;
-      const double c = std::exp(-(double)(dy * dy + dx * dx) / (double)p->sigma_s);
+      const double c = p->spatial_weight == 1 ? std::pow((double)p->sigma_s, (double)(std::abs(dy) + std::abs(dx)))
+                                              : std::exp(-(double)(dy * dy + dx * dx) / (double)p->sigma_s);
       g.cd[d] = (float)c;
       g.cd2[d] = (float)(c * c);
       g.ody[d] = (signed char)dy;
@@ -199,7 +201,7 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   g.cg_tol = p->cg_tol;
   g.stop_tol = p->stop_tol;
   {
-    const int tmax = (g.U - 1) / 2 > (g.V - 1) / 2 ? (g.U - 1) / 2 : (g.V - 1) / 2;
+    const int tmax = g.U / 2 > g.V / 2 ? g.U / 2 : g.V / 2;  // largest |angular offset| (odd or even grid)
     g.halo = (int)std::ceil((double)tmax * (double)p->disp_bound) + 1;
   }
   if (!choose_tiles(g, err)) return false;
@@ -641,6 +643,77 @@ lfsr_status lfsr_occlusion_weight(lfsr_handle* h, const float* d_lr, const float
   const float c2 = std::isinf(sigma_o2) ? 0.f : (float)(0.5 / ((double)sigma_o2 * sigma_o2));
   launch_occ_final(g, dref, acc, g.sk > 1 ? (float)(1.0 / (g.sk - 1)) : 0.f, c1, c2, d_occ_out, s);
   return check_hip(h, "lfsr_occlusion_weight");
+}
+
+lfsr_status lfsr_gd(lfsr_handle* h, int32_t iters, float step, int32_t line_search, double* h_hist,
+                    void* hip_stream) {
+  lfsr_status st = usable(h);
+  if (st) return st;
+  if (!h->bound) return set_err(h, LFSR_ESTATE, "lfsr_gd before lfsr_init");
+  if (h->b.st != kStF32) return set_err(h, LFSR_EINVAL, "lfsr_gd needs FP32 storage");
+  if (iters < 0 || !(step > 0.f) || !std::isfinite(step) || (line_search != 0 && line_search != 1))
+    return set_err(h, LFSR_EINVAL, "lfsr_gd: iters >= 0, step > 0 and line_search 0 or 1 required");
+  const Geom& g = h->plan.g;
+  const Bufs& b = h->b;
+  hipStream_t s = S(hip_stream);
+  float* x = (float*)b.x;
+  float* xc = b.vs;  // trial point of the line search
+  double dev[2];
+  auto read = [&](double* out) -> bool {  // (J, |g|^2) of the last evaluations
+    if (hipMemcpyAsync(dev, &b.sc->gd_cost, 2 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return false;
+    out[0] = dev[0];
+    out[1] = dev[1];
+    return true;
+  };
+  // weights fixed at the starting point (the cost every solver minimises here)
+  launch_edge(g, x, kStF32, h->occ, b.m, s, b, 0);
+  launch_gd_cost(g, x, h->disp, h->y, s, b);  // one CU: A and S
+  launch_gd_grad(g, h->disp, s, b);           // one CU: A^T and S^T
+  double cur[2];
+  if (!read(cur)) return check_hip(h, "lfsr_gd read");
+  double cu = 2.0, eta = step;
+  if (h_hist) {
+    h_hist[0] = cur[0];
+    h_hist[1] = cu;
+    h_hist[2] = 0.0;
+  }
+  for (int it = 1; it <= iters; ++it) {
+    if (!line_search) {
+      launch_gd_step(g, x, step, x, s, b);
+      launch_gd_cost(g, x, h->disp, h->y, s, b);
+      launch_gd_grad(g, h->disp, s, b);
+      cu += 2.0;
+      if (!read(cur)) return check_hip(h, "lfsr_gd read");
+    } else {
+      // backtracking by halves from twice the last accepted step; Armijo
+      // sufficient decrease J(x - eta g) <= J(x) - 1e-4 eta |g|^2
+      eta = it == 1 ? (double)step : 2.0 * eta;
+      for (int trial = 0; trial < 30; ++trial) {
+        launch_gd_step(g, x, (float)eta, xc, s, b);
+        launch_gd_cost(g, xc, h->disp, h->y, s, b);
+        cu += 1.0;
+        double trial_val[2];
+        if (!read(trial_val)) return check_hip(h, "lfsr_gd read");
+        if (trial_val[0] <= cur[0] - 1e-4 * eta * cur[1]) {
+          if (hipMemcpyAsync(x, xc, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            return check_hip(h, "lfsr_gd accept");
+          launch_gd_grad(g, h->disp, s, b);
+          cu += 1.0;
+          if (!read(cur)) return check_hip(h, "lfsr_gd read");
+          break;
+        }
+        eta *= 0.5;
+      }
+    }
+    if (h_hist) {
+      h_hist[3 * it + 0] = cur[0];
+      h_hist[3 * it + 1] = cu;
+      h_hist[3 * it + 2] = line_search ? eta : (double)step;
+    }
+  }
+  return check_hip(h, "lfsr_gd");
 }
 
 lfsr_status lfsr_bicubic(lfsr_handle* h, const float* d_lr_view, float* d_hr_out, void* hip_stream) {

@@ -28,7 +28,7 @@ constexpr int kRedBlocks = 512;   // max grid of the element-wise CG kernels (= 
 
 // Problem geometry and model constants, passed by value to every kernel.
 struct Geom {
-  int U, V, sk, kref;         // angular grid, views, reference (centre) view
+  int U, V, sk, kref;         // angular grid, views, reference view (angular offset (0, 0))
   int sy, sx, zeta, H, W;     // LR size, scale, HR size
   long long q, p;             // LR and HR pixel counts
   int kb, rb;                 // blur size and radius
@@ -78,6 +78,8 @@ struct DevScalars {
   int stop_pending;
   int iters_done;
   int err_flags;    // bit 0: non-finite input, bit 1: |disp| > disp_bound
+  double gd_cost;   // gradient-descent baselines: J at the last evaluated point
+  double gd_gnorm;  // and |g|^2 of the last gradient
 };
 
 // Storage element types of the solver state (the values of lfsr_storage).
@@ -172,6 +174,13 @@ void launch_to_float(const void* in, int st, float* out, long long n, hipStream_
 void launch_from_float(const float* in, void* out, int st, long long n, hipStream_t s);
 void launch_zero(void* p, int st, long long n, hipStream_t s);
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s);
+// gradient-descent baselines (FP32 state): cost parts at xp (J -> sc->gd_cost;
+// q = lambda1 sgn(r) + 2 lambda2 r into b.lr over its t = A xp; S^T sgn(g)
+// into b.hp); gradient g = b.r + b.hp into b.pv (|g|^2 -> sc->gd_gnorm);
+// out = x - eta g
+void launch_gd_cost(const Geom& g, const float* xp, const float* disp, const float* y, hipStream_t s, const Bufs& b);
+void launch_gd_grad(const Geom& g, const float* disp, hipStream_t s, const Bufs& b);
+void launch_gd_step(const Geom& g, const float* x, float eta, float* out, hipStream_t s, const Bufs& b);
 // occlusion weight: acc += squared projection error of view k; then the weight
 void launch_occ_acc(const Geom& g, const float* lref, const float* lk, const float* disp, int k, float* acc,
                     hipStream_t s);

@@ -1866,6 +1866,89 @@ __global__ __launch_bounds__(kThreads) void k_bicubic(Geom g, const float* __res
   }
 }
 
+// Gradient-descent baselines (sec 7.1), data part: over t = A x in `lr`,
+// r = t - y, q = lambda1 sgn(r) + 2 lambda2 r written back over t, and the
+// block's share of lambda1 |r| + lambda2 r^2.
+__global__ __launch_bounds__(kThreads) void k_gd_data(Geom g, const float* __restrict__ y, float* __restrict__ lr,
+                                                      double* __restrict__ part) {
+  const long long n = (long long)g.sk * g.q;
+  double acc = 0.0;
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads) {
+    const float r = lr[o] - y[o];
+    const float sg = (float)((r > 0.f) - (r < 0.f));
+    lr[o] = fmaf(2.f * g.lambda2, r, g.lambda1 * sg);
+    acc += (double)g.lambda1 * fabs((double)r) + (double)g.lambda2 * (double)r * (double)r;
+  }
+  double v[1] = {acc};
+  block_sum<1, 4>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Regulariser part: at pixel z, the cost share sum_d c_d m(z) |x(z) - x(z+d)|
+// and the subgradient S^T sgn(g) = sum_d c_d [m(z) sgn(x(z) - x(z+d))
+// - m(z-d) sgn(x(z-d) - x(z))] (pairs leaving the image are dropped;
+// sgn(0) = 0).  Plain gathers: a baseline, not a tuned stencil.
+__global__ __launch_bounds__(kThreads) void k_gd_tv(Geom g, const float* __restrict__ x, const float* __restrict__ m,
+                                                    float* __restrict__ out, double* __restrict__ part) {
+  double acc = 0.0;
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
+    const int Y = (int)(o / g.W), X = (int)(o - (long long)Y * g.W);
+    const float xz = x[o], mz = m[o];
+    float sub = 0.f, cost = 0.f;
+    for (int d = 0; d < g.sd; ++d) {
+      const int dy = g.ody[d], dx = g.odx[d];
+      const float c = g.cd[d];
+      if (Y + dy >= 0 && Y + dy < g.H && X + dx >= 0 && X + dx < g.W) {
+        const float df = xz - x[o + (long long)dy * g.W + dx];
+        cost = fmaf(c * mz, fabsf(df), cost);
+        sub = fmaf(c * mz, (float)((df > 0.f) - (df < 0.f)), sub);
+      }
+      if (Y - dy >= 0 && Y - dy < g.H && X - dx >= 0 && X - dx < g.W) {
+        const long long q = o - (long long)dy * g.W - dx;
+        const float df = x[q] - xz;
+        sub = fmaf(-c * m[q], (float)((df > 0.f) - (df < 0.f)), sub);
+      }
+    }
+    out[o] = sub;
+    acc += (double)cost;
+  }
+  double v[1] = {acc};
+  block_sum<1, 4>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// Fixed-order total of one or two partial arrays into a device scalar.
+__global__ __launch_bounds__(kThreads) void k_gd_total(const double* __restrict__ p0, int n0,
+                                                       const double* __restrict__ p1, int n1,
+                                                       double* __restrict__ dst) {
+  double a[1], b[1];
+  sum_parts<1>(p0, n0, a);
+  if (n1 > 0) sum_parts<1>(p1, n1, b);
+  else b[0] = 0.0;
+  if (threadIdx.x == 0) *dst = a[0] + b[0];
+}
+
+// g = a + t and the block's share of |g|^2.
+__global__ __launch_bounds__(kThreads) void k_gd_grad(Geom g, const float* __restrict__ a, const float* __restrict__ t,
+                                                      float* __restrict__ gout, double* __restrict__ part) {
+  double acc = 0.0;
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < g.p; o += (long long)gridDim.x * kThreads) {
+    const float v = a[o] + t[o];
+    gout[o] = v;
+    acc += (double)v * (double)v;
+  }
+  double v[1] = {acc};
+  block_sum<1, 4>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
+}
+
+// out = x - eta g (out may be x: no restrict on those two)
+__global__ __launch_bounds__(kThreads) void k_gd_step(const float* x, const float* __restrict__ gr, float eta,
+                                                      float* out, long long n) {
+  for (long long o = blockIdx.x * (long long)kThreads + threadIdx.x; o < n; o += (long long)gridDim.x * kThreads)
+    out[o] = fmaf(-eta, gr[o], x[o]);
+}
+
 // Occlusion weight (sec 3.4, eq. weight_occ), projection-error part: for one
 // view k, acc += (L_ref(z) - L_k(z - theta_k w(z)))^2 at every HR pixel z, with
 // L_ref, L_k the bicubic up-sampled views (the x0 operator) and L_k read
@@ -2407,6 +2490,37 @@ void launch_zero(void* p, int st, long long n, hipStream_t s) {
 
 void launch_bicubic(const Geom& g, const float* lrv, float* out, hipStream_t s) {
   hipLaunchKernelGGL(k_bicubic, dim3(grid1d(g.p)), dim3(kThreads), 0, s, g, lrv, out);
+}
+
+void launch_gd_cost(const Geom& g, const float* xp, const float* disp, const float* y, hipStream_t s, const Bufs& b) {
+  float* lr = (float*)b.lr;
+  launch_forward(g, xp, disp, lr, s, b, 0);
+  const unsigned nb = (unsigned)g.red_blocks;
+  hipLaunchKernelGGL(k_gd_data, dim3(nb), dim3(kThreads), 0, s, g, y, lr, b.p_rr[0]);
+  if (g.sd > 0)
+    hipLaunchKernelGGL(k_gd_tv, dim3(nb), dim3(kThreads), 0, s, g, xp, (const float*)b.m, b.hp, b.p_rr[1]);
+  else
+    launch_fill(b.hp, g.p, 0.f, s);
+  hipLaunchKernelGGL(k_gd_total, dim3(1), dim3(kThreads), 0, s, (const double*)b.p_rr[0], (int)nb,
+                     (const double*)b.p_rr[1], g.sd > 0 ? (int)nb : 0, &b.sc->gd_cost);
+}
+
+void launch_gd_grad(const Geom& g, const float* disp, hipStream_t s, const Bufs& b) {
+  const float* q = (const float*)b.lr;
+  const int npmax = launch_absmax(g, q, (long long)g.sk * g.q, s, b);
+  launch_adjoint(g, q, kStF32, disp, s, b, 0, npmax);
+  launch_merge(g, b.r, s, b, 0);
+  const unsigned nb = (unsigned)g.red_blocks;
+  hipLaunchKernelGGL(k_gd_grad, dim3(nb), dim3(kThreads), 0, s, g, (const float*)b.r, (const float*)b.hp, b.pv,
+                     b.p_rr[0]);
+  hipLaunchKernelGGL(k_gd_total, dim3(1), dim3(kThreads), 0, s, (const double*)b.p_rr[0], (int)nb,
+                     (const double*)nullptr, 0, &b.sc->gd_gnorm);
+}
+
+void launch_gd_step(const Geom& g, const float* x, float eta, float* out, hipStream_t s, const Bufs& b) {
+  (void)b;
+  hipLaunchKernelGGL(k_gd_step, dim3(grid1d(g.p)), dim3(kThreads), 0, s, x, (const float*)b.pv, eta, out,
+                     (long long)g.p);
 }
 
 void launch_occ_acc(const Geom& g, const float* lref, const float* lk, const float* disp, int k, float* acc,

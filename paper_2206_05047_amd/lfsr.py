@@ -26,7 +26,7 @@ EXPORTS = [
     "lfsr_normal", "lfsr_edge_weight", "lfsr_bicubic", "lfsr_profile_begin", "lfsr_profile_end",
     "lfsr_pool_create", "lfsr_pool_destroy", "lfsr_pool_last_error", "lfsr_pool_submit", "lfsr_pool_tick",
     "lfsr_pool_poll", "lfsr_pool_info", "lfsr_solve_noalloc",
-    "lfsr_occlusion_weight",
+    "lfsr_occlusion_weight", "lfsr_gd",
 ]
 LFSR_K_FORWARD, LFSR_K_ADJOINT, LFSR_K_NLTV, LFSR_K_NORMAL, LFSR_K_CG, LFSR_K_OTHER, LFSR_K_COUNT = range(7)
 KERNEL_KINDS = ["forward", "adjoint", "nltv", "normal", "cg", "other"]
@@ -47,6 +47,7 @@ class lfsr_params(ctypes.Structure):
         ("cg_tol", ctypes.c_float), ("stop_tol", ctypes.c_float),
         ("disp_bound", ctypes.c_float),
         ("storage", ctypes.c_int32),
+        ("spatial_weight", ctypes.c_int32),
     ]
 
 
@@ -105,6 +106,8 @@ def load():
     lib.lfsr_edge_weight.restype = I
     lib.lfsr_occlusion_weight.argtypes = [H, F, F, ctypes.c_float, ctypes.c_float, F, V]
     lib.lfsr_occlusion_weight.restype = I
+    lib.lfsr_gd.argtypes = [H, I, ctypes.c_float, I, ctypes.POINTER(ctypes.c_double), V]
+    lib.lfsr_gd.restype = I
     lib.lfsr_bicubic.argtypes = [H, F, F, V]
     lib.lfsr_bicubic.restype = I
     lib.lfsr_profile_begin.argtypes = [H, ctypes.c_uint32, I]
@@ -154,6 +157,7 @@ def make_params(cfg: dict, **over) -> lfsr_params:
         admm_penalty=c["theta"], admm_iters=c["n_iter"], cg_iters=c["cg_iter"],
         cg_tol=c.get("cg_tol", 0.0), stop_tol=c.get("stop_tol", 0.0),
         disp_bound=c.get("disp_bound", 2.0), storage=c.get("storage", LFSR_F32),
+        spatial_weight=c.get("weight_kind", 0),
     )
 
 
@@ -289,6 +293,16 @@ class Solver:
         self._check(self.lib.lfsr_occlusion_weight(self.handle, _ptr(lr), _ptr(disp), float(sigma_o1),
                                                    float(sigma_o2), _ptr(out), _stream(stream)), self.handle)
         return out
+
+    def lfsr_gd(self, iters, step, line_search=False, stream=None):
+        """Gradient-descent baseline on the bound inputs; returns the
+        [iters + 1][3] history (J, computation units, step)."""
+        import numpy as np
+        hist = (ctypes.c_double * (3 * (int(iters) + 1)))()
+        self._check(self.lib.lfsr_gd(self.handle, int(iters), float(step), int(bool(line_search)),
+                                     ctypes.cast(hist, ctypes.POINTER(ctypes.c_double)), _stream(stream)),
+                    self.handle)
+        return np.frombuffer(hist, dtype=np.float64).reshape(int(iters) + 1, 3).copy()
 
     def lfsr_bicubic(self, lr_view, out=None, stream=None):
         out = self._empty(self.H, self.W) if out is None else out

@@ -70,11 +70,11 @@ def test_16bit_storage_halves_the_stored_fields(lfsr, name):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("ang_rows", 2), ("ang_cols", 0), ("lr_h", 0), ("scale", 0), ("scale", 9), ("n_disp", 2), ("n_disp", 8),
+    ("ang_rows", 64), ("ang_cols", 0), ("lr_h", 0), ("scale", 0), ("scale", 9), ("n_disp", 2), ("n_disp", 8),
     ("blur_size", 4), ("blur_size", 33), ("lambda1", -1.0), ("nltv_window", 4), ("nltv_window", 17),
     ("sigma_s", 0.0), ("sigma_e", 0.0), ("admm_penalty", 0.0), ("admm_iters", 0), ("cg_iters", -1),
     ("cg_tol", -1.0), ("stop_tol", float("nan")), ("disp_bound", 0.0), ("disp_bound", float("inf")),
-    ("reweight", 2), ("storage", 7),
+    ("reweight", 2), ("storage", 7), ("spatial_weight", 2),
 ])
 def test_invalid_params_rejected(lfsr, field, value):
     p = _params(lfsr)
@@ -166,3 +166,15 @@ def test_per_view_maps_accepted(lfsr):
     one = lfsr.workspace_bytes(_params(lfsr, "c1"))
     per = lfsr.workspace_bytes(_params(lfsr, "c1", n_disp=9))
     assert per > 0 and abs(per - one) < 0.2 * one
+
+
+def test_btv_weight_needs_alpha_at_most_one(lfsr):
+    assert lfsr.workspace_bytes(_params(lfsr, weight_kind=1, sigma_s=0.7)) > 0
+    p = _params(lfsr, weight_kind=1, sigma_s=1.5)
+    assert lfsr.load().lfsr_workspace_bytes(ctypes.byref(p)) == 0
+    assert "BTV" in lfsr.last_error()
+
+
+def test_even_angular_grid_accepted(lfsr):
+    """The 2 x 2 images of the x2 multi-image workload: offsets 0..1."""
+    assert lfsr.workspace_bytes(_params(lfsr, U=2, V=2)) > 0
