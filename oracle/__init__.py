@@ -45,6 +45,7 @@ class OrcParams(ctypes.Structure):
         ("cg_iter", ctypes.c_int32),
         ("cg_tol", ctypes.c_double),
         ("weight_kind", ctypes.c_int32),
+        ("blur_taps", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -124,6 +125,7 @@ class Problem:
     reweight: int = 1
     n_disp: int = 1
     weight_kind: int = 0
+    blur_taps: object = None  # None: Gaussian; else a [kb][kb] correlation kernel
 
     @classmethod
     def from_any(cls, cfg) -> "Problem":
@@ -160,7 +162,15 @@ class Problem:
             float(self.lambda1), float(self.lambda2), self.win, float(self.sigma_s),
             float(self.sigma_e), int(self.reweight), float(self.theta), self.cg_iter,
             float(self.cg_tol), int(self.weight_kind),
+            _d(self._taps) if self._taps is not None else None,
         )
+
+    def __post_init__(self):
+        self._taps = None
+        if self.blur_taps is not None:
+            t = np.ascontiguousarray(np.asarray(self.blur_taps, dtype=np.float64))
+            assert t.shape == (self.kb, self.kb), (t.shape, self.kb)
+            self._taps = t
 
 
 def _d(a: np.ndarray):

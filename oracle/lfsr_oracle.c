@@ -60,6 +60,7 @@ typedef struct {
   int32_t cg_iter;       /* K */
   double cg_tol;         /* tau */
   int32_t weight_kind;   /* spatial weight: 0 exp(-|d|^2/sigma_s); 1 BTV sigma_s^(|dy|+|dx|) */
+  const double* blur_taps;  /* NULL: the Gaussian below; else the kb x kb correlation kernel, row-major */
 } orc_params;
 
 /* ------------------------------------------------------------------ sizes */
@@ -99,8 +100,14 @@ static const double* disp_of(const orc_params* p, const double* disp, int k) {
 /* ------------------------------------------------------------ blur kernel */
 
 /* sec 4.1: B is a Gaussian kernel; we take the 2-D kernel
- * h(a,b) ~ exp(-(a^2+b^2)/(2 sigma^2)) on the kb x kb grid, normalised to 1. */
+ * h(a,b) ~ exp(-(a^2+b^2)/(2 sigma^2)) on the kb x kb grid, normalised to 1.
+ * sec 7.1 models motion blur by another convolution kernel for B: given
+ * explicitly (blur_taps), it is used as is, with no symmetry assumed. */
 void orc_blur_kernel(const orc_params* p, double* h) {
+  if (p->blur_taps) {
+    memcpy(h, p->blur_taps, sizeof(double) * p->kb * p->kb);
+    return;
+  }
   int r = p->kb / 2;
   double s = 0.0;
   for (int a = -r; a <= r; ++a)

@@ -745,3 +745,54 @@ def test_gd_line_search_is_monotone_with_armijo_steps():
     J, cu = hist[:, 0], hist[:, 1]
     assert np.all(np.diff(J) <= 0) and J[-1] < J[0]
     assert np.all(np.diff(cu) >= 2)  # at least one trial and one adjoint per step
+
+
+# ---------------------------------------------------------------- general blur kernel (sec 7.1: motion blur)
+
+def motion_kernel(kb, angle_deg=45.0, length=None):
+    """A line (motion-blur) kernel on a kb x kb grid: samples along a segment
+    through the centre at the given angle, bilinearly splatted, normalised
+    to 1; off-centre weighting makes it non-symmetric."""
+    L = (kb - 1) if length is None else length
+    r = kb // 2
+    h = np.zeros((kb, kb))
+    t = np.linspace(-L / 2, L / 2, 8 * kb)
+    w = 1.0 + 0.8 * (t - t.min()) / (t.max() - t.min())  # heavier at one end: not symmetric
+    ang = np.deg2rad(angle_deg)
+    for tt, ww in zip(t, w):
+        yy, xx = r - tt * np.sin(ang), r + tt * np.cos(ang)
+        i0, j0 = int(np.floor(yy)), int(np.floor(xx))
+        fy, fx = yy - i0, xx - j0
+        for di, dj, c in ((0, 0, (1 - fy) * (1 - fx)), (0, 1, (1 - fy) * fx), (1, 0, fy * (1 - fx)), (1, 1, fy * fx)):
+            if 0 <= i0 + di < kb and 0 <= j0 + dj < kb:
+                h[i0 + di, j0 + dj] += ww * c
+    return h / h.sum()
+
+
+def test_explicit_blur_kernel_equals_scipy_correlate_and_is_not_symmetric():
+    h = motion_kernel(7)
+    assert np.abs(h - h[::-1, ::-1]).max() > 1e-3
+    o = _o(kb=7, blur_taps=h)
+    np.testing.assert_array_equal(o.blur_kernel(), h)
+    x = _rng(91).standard_normal(o.hr_shape)
+    ref = ndimage.correlate(x, h, mode="constant", cval=0.0)
+    np.testing.assert_allclose(o.blur(x), ref, rtol=0, atol=1e-14)
+
+
+def test_explicit_blur_adjoint_and_forward_composition():
+    """B^T of a non-symmetric kernel is its transpose (not B again), and
+    A_k = D B W_k with it; the adjoint of the whole forward model holds."""
+    h = motion_kernel(9, angle_deg=30.0)
+    o = _o(kb=9, zeta=2, blur_taps=h)
+    rng = _rng(92)
+    u, v = rng.standard_normal(o.hr_shape), rng.standard_normal(o.hr_shape)
+    assert abs(np.vdot(o.blur(u), v) - np.vdot(u, o.blur_t(v))) < 1e-12 * np.abs(u).sum() * np.abs(v).sum()
+    assert np.abs(o.blur_t(v) - o.blur(v)).max() > 1e-3
+    d = _disp_smooth(o, rng)
+    x = rng.standard_normal(o.hr_shape)
+    t = o.forward(x, d)
+    for k in (0, 4, 8):
+        np.testing.assert_allclose(t[k], o.down(o.blur(o.warp(x, d, k))), rtol=0, atol=1e-13)
+    e = rng.standard_normal(o.lr_shape)
+    lhs, rhs = np.vdot(t, e), np.vdot(x, o.adjoint(e, d))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
