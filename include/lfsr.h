@@ -108,6 +108,10 @@ typedef struct {
   int32_t storage;            /* lfsr_storage of the solver state (see below) */
   int32_t spatial_weight;     /* NLTV spatial weight of offset d: 0 = exp(-|d|^2 / sigma_s) (sec 3.4);
                                  1 = BTV, sigma_s^(|dy|+|dx|) with 0 < sigma_s <= 1 (sec 7.3) */
+  const float* blur_taps;     /* NULL: the Gaussian of blur_size / blur_sigma; else host memory holding an
+                                 explicit [blur_size][blur_size] correlation kernel, row-major, blur_size odd
+                                 <= 15, read by lfsr_create / lfsr_workspace_bytes only (sec 7.1 models motion
+                                 blur this way; no symmetry is assumed: B^T is its transpose) */
 } lfsr_params;
 
 #define LFSR_NSTAT 6

@@ -160,6 +160,17 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
   if (kb < 1 || kb > kMaxTaps || kb % 2 == 0) return fail(err, "blur_size must be odd in 1..31");
   g.kb = kb;
   g.rb = kb / 2;
+  g.blur2d = p->blur_taps ? 1 : 0;
+  if (g.blur2d) {  // an explicit kernel (sec 7.1: motion blur), used as given
+    if (p->blur_size < 1 || p->blur_size > kMax2DTaps || p->blur_size % 2 == 0)
+      return fail(err, "an explicit blur kernel needs an odd blur_size in 1..15");
+    g.kb = p->blur_size;
+    g.rb = g.kb / 2;
+    for (int i = 0; i < g.kb * g.kb; ++i) {
+      if (!std::isfinite(p->blur_taps[i])) return fail(err, "blur_taps must be finite");
+      pl->taps2d[i] = p->blur_taps[i];
+    }
+  }
   {
     double s = 0.0, t[kMaxTaps];
     for (int a = 0; a < kb; ++a) {
@@ -240,6 +251,7 @@ bool make_plan(const lfsr_params* p, Plan* pl, std::string* err) {
     pl->off_pcnt = take((size_t)ag.x * ag.y * ag.z * sizeof(int));
   }
   pl->off_stats = take((size_t)p->admm_iters * LFSR_NSTAT * sizeof(double));
+  pl->off_taps = take(g.blur2d ? (size_t)g.kb * g.kb * sizeof(float) : 0);
   pl->bytes = o;
   return true;
 }
@@ -359,6 +371,13 @@ void restore_counts(lfsr_handle* h, const float* d_disp, hipStream_t s) {
   if (h->disp && h->disp != d_disp) launch_adjcount(h->plan.g, h->disp, s, h->b);
 }
 
+// An explicit blur kernel lives in the workspace; every entry point that
+// applies B enqueues its (tiny) upload first, so that it does not depend on
+// which call came before.
+void upload_taps(lfsr_handle* h, hipStream_t s) {
+  if (h->plan.g.blur2d) launch_set_taps(h->plan.g, h->plan.taps2d, s);
+}
+
 // Carve a workspace into the buffers of a handle (the layout of make_plan).
 void bind_workspace(lfsr_handle* h, const lfsr_params* p, const Plan& pl, char* w) {
   h->prm = *p;
@@ -386,6 +405,7 @@ void bind_workspace(lfsr_handle* h, const lfsr_params* p, const Plan& pl, char* 
   h->b.p_max = (float*)(w + pl.off_pmax);
   h->b.p_cnt = (int*)(w + pl.off_pcnt);
   h->b.stats = (double*)(w + pl.off_stats);
+  h->plan.g.taps2d = pl.g.blur2d ? (const float*)(w + pl.off_taps) : nullptr;
   h->n_done = 0;
   h->bound = false;
   h->broken = false;
@@ -443,6 +463,7 @@ lfsr_status lfsr_init(lfsr_handle* h, const float* d_lr, const float* d_disp, co
   h->y = d_lr;
   h->disp = d_disp;
   h->occ = d_occ;
+  upload_taps(h, s);
   launch_reset(0, s, h->b);
   launch_check(g, d_lr, d_disp, d_occ, s, h->b);
   launch_adjcount(g, d_disp, s, h->b);
@@ -503,6 +524,7 @@ lfsr_status lfsr_write_state(lfsr_handle* h, const float* d_x, const float* d_wd
   if (n_done < 0) return set_err(h, LFSR_EINVAL, "n_done must be >= 0");
   if (!h->y) return set_err(h, LFSR_ESTATE, "lfsr_write_state needs inputs bound by lfsr_init first");
   hipStream_t s = S(hip_stream);
+  upload_taps(h, s);
   launch_reset(n_done, s, h->b);
   if (h->b.st == kStF32) {
     if (hipMemcpyAsync(h->b.x, d_x, (size_t)g.p * 4, hipMemcpyDeviceToDevice, s) != hipSuccess ||
@@ -576,6 +598,7 @@ lfsr_status lfsr_forward(lfsr_handle* h, const float* d_x, const float* d_disp, 
   lfsr_status st = usable(h);
   if (st) return st;
   if (!d_x || !d_disp || !d_lr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
+  upload_taps(h, S(hip_stream));
   launch_forward(h->plan.g, d_x, d_disp, d_lr_out, S(hip_stream), h->b, 0);
   return check_hip(h, "lfsr_forward");
 }
@@ -585,6 +608,7 @@ lfsr_status lfsr_adjoint(lfsr_handle* h, const float* d_lr, const float* d_disp,
   if (st) return st;
   if (!d_lr || !d_disp || !d_hr_out) return set_err(h, LFSR_EINVAL, "NULL pointer");
   const Geom& g = h->plan.g;
+  upload_taps(h, S(hip_stream));
   const int npmax = launch_absmax(g, d_lr, (long long)g.sk * g.q, S(hip_stream), h->b);
   launch_adjcount(g, d_disp, S(hip_stream), h->b);
   launch_adjoint(g, d_lr, kStF32, d_disp, S(hip_stream), h->b, 0, npmax);
@@ -601,6 +625,7 @@ lfsr_status lfsr_normal(lfsr_handle* h, const float* d_p, const float* d_disp, c
   if (d_out == d_p || d_out == d_m) return set_err(h, LFSR_EINVAL, "d_out must not alias d_p or d_m");
   const Geom& g = h->plan.g;
   hipStream_t s = S(hip_stream);
+  upload_taps(h, s);
   launch_forward_cg(g, d_p, d_disp, s, h->b, 0);
   launch_adjcount(g, d_disp, s, h->b);
   launch_adjoint(g, h->b.lr, h->b.st, d_disp, s, h->b, 0, forward_blocks(g));

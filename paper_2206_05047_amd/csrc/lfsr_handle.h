@@ -14,7 +14,8 @@ namespace lfsr {
 struct Plan {
   Geom g;
   size_t off_x, off_dx, off_m, off_vs, off_r, off_pv, off_hp, off_wd, off_ws0, off_ws1, off_lr, off_adj, off_pwzd,
-      off_ptv, off_prr0, off_prr1, off_pphp, off_pmax, off_pcnt, off_stats, off_sc;
+      off_ptv, off_prr0, off_prr1, off_pphp, off_pmax, off_pcnt, off_stats, off_sc, off_taps;
+  float taps2d[kMax2DTaps * kMax2DTaps];  // explicit blur kernel (host copy), when g.blur2d
   size_t bytes;
 };
 

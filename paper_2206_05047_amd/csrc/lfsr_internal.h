@@ -7,6 +7,7 @@
 namespace lfsr {
 
 constexpr int kMaxTaps = 31;      // blur size limit
+constexpr int kMax2DTaps = 15;    // size limit of an explicit (non-separable) blur kernel
 constexpr int kMaxWin = 15;       // NLTV window limit
 constexpr int kMaxOffsets = kMaxWin * kMaxWin - 1;
 constexpr int kThreads = 256;     // every kernel runs 256-thread (4 x wave64) blocks
@@ -33,6 +34,8 @@ struct Geom {
   long long q, p;             // LR and HR pixel counts
   int kb, rb;                 // blur size and radius
   float g[kMaxTaps];          // normalised 1-D Gaussian taps (2-D kernel = g x g)
+  int blur2d;                 // 1: explicit kb x kb correlation kernel at taps2d (tiled kernels only)
+  const float* taps2d;        // its device copy in the workspace (set when the workspace is bound)
   int win, rw, sd;            // NLTV window, radius, number of offsets
   float cd[kMaxOffsets];      // spatial weight exp(-|d|^2/sigma_s) of offset d
   float cd2[kMaxOffsets];     // its square
@@ -188,6 +191,8 @@ void launch_occ_final(const Geom& g, const float* disp, const float* acc, float 
                       float* out, hipStream_t s);
 void launch_check(const Geom& g, const float* y, const float* disp, const float* occ, hipStream_t s, const Bufs& b);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
+// copy an explicit blur kernel (kb * kb floats, host) to g.taps2d
+void launch_set_taps(const Geom& g, const float* host_taps, hipStream_t s);
 void launch_reset(int n_done, hipStream_t s, const Bufs& b);
 void launch_copy_ws(float* out, long long n, hipStream_t s, const Bufs& b);
 

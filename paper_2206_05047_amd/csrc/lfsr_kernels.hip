@@ -243,6 +243,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
   float* xs = smem;          // [SY][SX] source tile, zero outside the image
   float* wv = xs + SY * SX;  // [NY][NX] warped values of the current view
   float* hb = wv + NPOS;     // [NY][tlx] horizontal blur at lattice columns
+  float* t2 = hb + NH;       // [kb][kb] explicit blur kernel (g.blur2d)
+  if (g.blur2d)
+    for (int i = threadIdx.x; i < kb * kb; i += kThreads) t2[i] = g.taps2d[i];
   const int i0 = blockIdx.y * tly, j0 = blockIdx.x * tlx;
   const int Yp0 = i0 * zeta - rb, Xp0 = j0 * zeta - rb;
   const int tid = threadIdx.x;
@@ -337,6 +340,16 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
       if (idx < NPOS) wv[idx] = val[s];
     }
     __syncthreads();
+    float t = 0.f;
+    if (g.blur2d) {
+      // explicit kernel: the 2-D correlation at the lattice point, from the warped values
+      if (vout) {
+        const float* wp = wv + li * zeta * NX + lj * zeta;
+        for (int a = 0; a < kb; ++a)
+          for (int b = 0; b < kb; ++b) t = fmaf(t2[a * kb + b], wp[a * NX + b], t);
+      }
+      __syncthreads();  // reads of wv precede the next view's stores
+    } else {
     // B, horizontal pass, only at the lattice columns D keeps
     float hsum[kFwdHSlots];
 #pragma unroll
@@ -354,14 +367,17 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
       if (idx < NH) hb[idx] = hsum[s];
     }
     __syncthreads();
-    // B, vertical pass, only at the lattice rows; then the fused epilogue
+    // B, vertical pass, only at the lattice rows
     if (vout) {
-      float t = 0.f;
 #pragma unroll
       for (int a = 0; a < (KBT > 0 ? KBT : kMaxTaps); ++a) {
         if (KBT == 0 && a >= kb) break;
         t = fmaf(g.g[a], hb[voff + a * tlx], t);
       }
+    }
+    }
+    // the fused epilogue
+    if (vout) {
       if constexpr (!WZD) {
         const TO ts = (TO)t;
         out[o] = ts;
@@ -696,7 +712,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
   long long* acc = smem8;                          // [EY][EX] fixed-point accumulator
   float* gs = smem + 2 * EY * EX;                  // [PAD + kb] taps, zeros below
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  float* t2 = gs + PAD + kb + 4 * (ETS + HVS);     // [kb][kb] explicit blur kernel (g.blur2d)
   float* e_ = gs + PAD + kb + wave * (ETS + HVS);  // wave-private LR rows (zero-padded)
+  if (g.blur2d)
+    for (int i = tid; i < kb * kb; i += kThreads) t2[i] = g.taps2d[i];
   float* h_ = e_ + ETS;                            // wave-private vertical pass
   for (int idx = tid; idx < EY * EX; idx += kThreads) acc[idx] = 0;
   for (int idx = tid; idx < PAD + kb; idx += kThreads) gs[idx] = idx < PAD ? 0.f : g.g[idx - PAD];
@@ -747,7 +766,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
   }
   // scatter pixels (wave row r, col lx): disparity (clamped), horizontal base/tap, accumulator base
   float om[kAdjSlots];
-  int hbase[kAdjSlots], htap[kAdjSlots], abase[kAdjSlots], dofs[kAdjSlots];
+  int hbase[kAdjSlots], htap[kAdjSlots], abase[kAdjSlots], dofs[kAdjSlots], ebase2[kAdjSlots], tapy[kAdjSlots],
+      tapx[kAdjSlots];
   bool act[kAdjSlots];
   const bool per_view = g.n_disp > 1;  // view k's own map ([k][H][W]), loaded per view
 #pragma unroll
@@ -764,6 +784,12 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
     hbase[s] = act[s] ? r * LX + lq + mlo + ci : 0;
     htap[s] = PAD + ph - zeta * mlo + rb;
     abase[s] = (ly + h) * EX + (lx + h);
+    if (g.blur2d) {  // explicit kernel: e_ row / tap row of the first lattice row in reach (the columns as above)
+      const int phy = ly % zeta, mloy = floordiv(phy - rb + zeta - 1, zeta);
+      ebase2[s] = act[s] ? ((Y0 + ly) / zeta + mloy - li0) * LX + lq + mlo + ci : 0;
+      tapy[s] = phy - zeta * mloy + rb;  // kernel row / column of the first lattice point (may be out of range)
+      tapx[s] = ph - zeta * mlo + rb;
+    }
   }
 #pragma unroll
   for (int s = 0; s < kAdjSlots; ++s) om[s] = act[s] ? fminf(fmaxf(om[s], -g.disp_bound), g.disp_bound) : 0.f;
@@ -829,6 +855,27 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
       }
     }
     __builtin_amdgcn_wave_barrier();
+    const float rho = (float)(kbcol - (g.V - 1) / 2);
+    float uu[kAdjSlots];
+    if (g.blur2d) {
+      // explicit kernel: B^T D^T as the 2-D correlation with the taps mirrored,
+      // over the lattice points within reach (scaled by S)
+#pragma unroll
+      for (int s = 0; s < kAdjSlots; ++s) {
+        float u = 0.f;
+        const int ay0 = tapy[s], bx0 = tapx[s];
+        for (int my = 0; my < MM; ++my) {
+          const int a = ay0 - zeta * my;
+          if (a < 0 || a >= kb) continue;
+          for (int mx = 0; mx < MM; ++mx) {
+            const int b = bx0 - zeta * mx;
+            if (b < 0 || b >= kb) continue;
+            u = fmaf(t2[a * kb + b], e_[ebase2[s] + my * LX + mx], u);
+          }
+        }
+        uu[s] = u * S;
+      }
+    } else {
     // B^T D^T, vertical
     float vv[kAdjVSlots];
 #pragma unroll
@@ -851,9 +898,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
       if (idx < RH * LX) h_[idx] = vv[s];
     }
     __builtin_amdgcn_wave_barrier();
-    // B^T D^T, horizontal (scaled by S); then W_k^T: send u back to the four taps W_k read
-    const float rho = (float)(kbcol - (g.V - 1) / 2);
-    float uu[kAdjSlots];
+    // B^T D^T, horizontal (scaled by S)
 #pragma unroll
     for (int s = 0; s < kAdjSlots; ++s) uu[s] = 0.f;
     if constexpr (MMT > 0) {
@@ -868,6 +913,8 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
         for (int s = 0; s < kAdjSlots; ++s) uu[s] = fmaf(gs[htap[s] - zeta * m] * S, h_[hbase[s] + m], uu[s]);
       }
     }
+    }
+    // then W_k^T: send u back to the four taps W_k read
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int s = 0; s < kAdjSlots; ++s) {
@@ -2010,6 +2057,14 @@ __global__ __launch_bounds__(kThreads) void k_check(Geom g, const float* __restr
   if (f) atomicOr(&sc->err_flags, f);
 }
 
+// Explicit blur kernel, passed by value (so the host copy need not outlive the launch).
+struct Taps2D {
+  float v[kMax2DTaps * kMax2DTaps];
+};
+__global__ void k_set_taps(Taps2D t, int n, float* __restrict__ dst) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = t.v[i];
+}
+
 // Fill n floats with a value (a kernel rather than hipMemsetAsync, so that
 // the sequence stays capturable in a graph).
 __global__ __launch_bounds__(kThreads) void k_fill(float* __restrict__ p, long long n, float v) {
@@ -2113,7 +2168,8 @@ size_t forward_lds(const Geom& g) {
   fwd_dims(g, NY, NX, SY, SX);
   if (g.f_col == 2) return sizeof(float) * (4 * (size_t)SY * SX + 8 * (size_t)g.f_tly * NX);
   if (g.f_col) return sizeof(float) * ((size_t)SY * kColPitch + 4 * (size_t)g.f_tly * NX);
-  return sizeof(float) * ((size_t)SY * SX + (size_t)NY * NX + (size_t)NY * g.f_tlx);
+  return sizeof(float) * ((size_t)SY * SX + (size_t)NY * NX + (size_t)NY * g.f_tlx +
+                          (g.blur2d ? (size_t)g.kb * g.kb : 0));
 }
 
 // (zeta, blur size) pairs with a compiled column-per-lane forward kernel, and
@@ -2127,7 +2183,7 @@ static constexpr int fwdcol_tly(int zeta, int kb) { return (void)zeta, (void)kb,
 bool forward_col_setup(Geom& g) {
   // the column kernels hold one disparity map in registers across all views;
   // per-view maps take the tiled kernels, which load the map per view
-  if (!fwdcol_shape(g.zeta, g.kb) || g.n_disp > 1) return false;
+  if (!fwdcol_shape(g.zeta, g.kb) || g.n_disp > 1 || g.blur2d) return false;
   Geom t = g;
   t.f_col = 1;
   t.f_tly = fwdcol_tly(g.zeta, g.kb);
@@ -2174,7 +2230,8 @@ size_t adjoint_lds(const Geom& g) {
   adj_dims(g, ci, LY, LX, MM, PAD);
   const int RH = g.a_th / 4, RL = RH / g.zeta + 2 * ci;
   const size_t ets = (size_t)(RL + MM) * LX, hvs = (size_t)RH * LX + MM;
-  return sizeof(float) * (2 * (size_t)g.a_ey * g.a_ex + PAD + g.kb + 4 * (ets + hvs));
+  return sizeof(float) * (2 * (size_t)g.a_ey * g.a_ex + PAD + g.kb + 4 * (ets + hvs) +
+                          (g.blur2d ? (size_t)g.kb * g.kb : 0));
 }
 
 bool adjoint_tile_ok(const Geom& g) {
@@ -2198,7 +2255,7 @@ dim3 adjoint_grid(const Geom& g) { return dim3(g.a_ntx, g.a_nty, g.a_vg); }
 static constexpr bool adjcol_shape(int zeta, int kb) { return fwdcol_shape(zeta, kb); }
 
 bool adjoint_col_setup(Geom& g) {
-  if (!adjcol_shape(g.zeta, g.kb) || g.n_disp > 1) return false;
+  if (!adjcol_shape(g.zeta, g.kb) || g.n_disp > 1 || g.blur2d) return false;
   Geom t = g;
   t.a_col = 1;
   t.a_th = adjcol_th(g.zeta);
@@ -2544,6 +2601,13 @@ void launch_check(const Geom& g, const float* y, const float* disp, const float*
 void launch_fill(float* p, long long n, float v, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3(grid1d(n)), dim3(kThreads), 0, s, p, n, v);
+}
+
+void launch_set_taps(const Geom& g, const float* host_taps, hipStream_t s) {
+  Taps2D t{};
+  const int n = g.kb * g.kb;
+  for (int i = 0; i < n; ++i) t.v[i] = host_taps[i];
+  hipLaunchKernelGGL(k_set_taps, dim3(1), dim3(256), 0, s, t, n, const_cast<float*>(g.taps2d));
 }
 
 void launch_reset(int n_done, hipStream_t s, const Bufs& b) {

@@ -48,6 +48,7 @@ class lfsr_params(ctypes.Structure):
         ("disp_bound", ctypes.c_float),
         ("storage", ctypes.c_int32),
         ("spatial_weight", ctypes.c_int32),
+        ("blur_taps", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -149,7 +150,12 @@ def make_params(cfg: dict, **over) -> lfsr_params:
     c.update(over)
     if isinstance(c.get("storage"), str):
         c["storage"] = STORAGE[c["storage"]]
-    return lfsr_params(
+    taps = c.get("blur_taps")
+    if taps is not None:  # explicit kernel: kept alive on the struct (lfsr_create copies it)
+        import numpy as np
+        taps = np.ascontiguousarray(np.asarray(taps, dtype=np.float32))
+        c["kb"] = int(taps.shape[0])
+    prm = lfsr_params(
         ang_rows=c["U"], ang_cols=c["V"], lr_h=c["sy"], lr_w=c["sx"], scale=c["zeta"],
         n_disp=c.get("n_disp", 1), blur_size=c["kb"], blur_sigma=c["sigma_b"],
         lambda1=c["lambda1"], lambda2=c["lambda2"], nltv_window=c["win"],
@@ -158,7 +164,10 @@ def make_params(cfg: dict, **over) -> lfsr_params:
         cg_tol=c.get("cg_tol", 0.0), stop_tol=c.get("stop_tol", 0.0),
         disp_bound=c.get("disp_bound", 2.0), storage=c.get("storage", LFSR_F32),
         spatial_weight=c.get("weight_kind", 0),
+        blur_taps=taps.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if taps is not None else None,
     )
+    prm._taps = taps
+    return prm
 
 
 def workspace_bytes(params: lfsr_params) -> int:

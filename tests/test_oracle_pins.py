@@ -11,6 +11,7 @@ import pytest
 from scipy import ndimage, optimize
 
 import oracle
+from helpers import motion_kernel
 
 TINY = dict(U=3, V=3, sy=6, sx=7, zeta=2, kb=5, sigma_b=1.0, lambda1=1.0, lambda2=1.0, win=3,
             sigma_s=1.0, sigma_e=1.0, theta=1.0, n_iter=5, cg_iter=5)
@@ -748,26 +749,6 @@ def test_gd_line_search_is_monotone_with_armijo_steps():
 
 
 # ---------------------------------------------------------------- general blur kernel (sec 7.1: motion blur)
-
-def motion_kernel(kb, angle_deg=45.0, length=None):
-    """A line (motion-blur) kernel on a kb x kb grid: samples along a segment
-    through the centre at the given angle, bilinearly splatted, normalised
-    to 1; off-centre weighting makes it non-symmetric."""
-    L = (kb - 1) if length is None else length
-    r = kb // 2
-    h = np.zeros((kb, kb))
-    t = np.linspace(-L / 2, L / 2, 8 * kb)
-    w = 1.0 + 0.8 * (t - t.min()) / (t.max() - t.min())  # heavier at one end: not symmetric
-    ang = np.deg2rad(angle_deg)
-    for tt, ww in zip(t, w):
-        yy, xx = r - tt * np.sin(ang), r + tt * np.cos(ang)
-        i0, j0 = int(np.floor(yy)), int(np.floor(xx))
-        fy, fx = yy - i0, xx - j0
-        for di, dj, c in ((0, 0, (1 - fy) * (1 - fx)), (0, 1, (1 - fy) * fx), (1, 0, fy * (1 - fx)), (1, 1, fy * fx)):
-            if 0 <= i0 + di < kb and 0 <= j0 + dj < kb:
-                h[i0 + di, j0 + dj] += ww * c
-    return h / h.sum()
-
 
 def test_explicit_blur_kernel_equals_scipy_correlate_and_is_not_symmetric():
     h = motion_kernel(7)
