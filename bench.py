@@ -381,7 +381,9 @@ def main():
         for st in ("f16", "bf16"):
             s16 = lfsr.Solver(lfsr.make_params(cfg, disp_bound=max(bound, 1e-3), storage=st))
             o16 = torch.empty_like(out)
+            s16.lfsr_profile_begin(capacity=N * (8 + 7 * K) + 64)  # the warm-up solve, timed per kernel kind
             s16.lfsr_solve(y, disp, out=o16, stats=False)
+            bd16 = s16.lfsr_profile_end()
             torch.cuda.synchronize()
             n16 = max(1, min(args.steps, 3))
             ta = time.perf_counter()
@@ -399,6 +401,8 @@ def main():
                 "psnr_f32": synth.psnr(ref, sc["x_gt"]),
                 "workspace_bytes": s16.bytes,
                 "steps": n16,
+                "kernel_ms_per_solve": {k: v[0] for k, v in bd16.items()},
+                "kernel_time_ratio_vs_f32": {k: bd16[k][0] / breakdown[k][0] for k in bd16 if breakdown[k][0] > 0},
                 **vs_oracle(x16),
             }
             s16.close()

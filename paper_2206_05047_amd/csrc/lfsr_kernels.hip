@@ -598,6 +598,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
       for (int i = 0; i < TLY; ++i) vb[i * NX + px] = acc[i];
     }
     __builtin_amdgcn_wave_barrier();  // the wave's LDS writes precede its reads below
+    float f_abs = 0.f, f_sq = 0.f, f_dw = 0.f;  // this view's NO outputs in FP32, then the FP64 totals
 #pragma unroll
     for (int s = 0; s < NO; ++s) {
       if (!oval[s]) continue;
@@ -618,11 +619,16 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
         out[o] = es;
         vmax = fmaxf(vmax, fabsf((float)es));
         wD[o] = (TO)wn;
-        const double rd = (double)r, dw = (double)wn - (double)w0[s];
-        s_abs += fabs(rd);
-        s_sq += rd * rd;
-        s_dw += dw * dw;
+        const float dw = wn - w0[s];
+        f_abs += fabsf(r);
+        f_sq = fmaf(r, r, f_sq);
+        f_dw = fmaf(dw, dw, f_dw);
       }
+    }
+    if constexpr (WZD) {
+      s_abs += (double)f_abs;
+      s_sq += (double)f_sq;
+      s_dw += (double)f_dw;
     }
     __builtin_amdgcn_wave_barrier();  // reads of vb complete before it is written again
   };
@@ -1283,6 +1289,15 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     sl[rr] = (ly + rw) * LXd + (lx + rw);
   }
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  // statistics: FP32 sums over at most 16 terms (one ring step of four
+  // offsets x four rows, relative error <= 16 u), added to the FP64 totals
+  float f_abs = 0.f, f_dw = 0.f;
+  auto flush = [&]() __attribute__((always_inline)) {
+    s_abs += (double)f_abs;
+    s_dw += (double)f_dw;
+    f_abs = 0.f;
+    f_dw = 0.f;
+  };
   // byte offset of pixel (Y[rr], X) within one dual plane (a plane is below
   // 2 GiB), so every dual access is a uniform plane pointer plus this offset
   unsigned boff[4];
@@ -1315,9 +1330,9 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
       const float wn = clipf(gv + w0[rr], g.clip);
       buf_store<T>(rn, boff[rr], (T)wn);
       if (fin) acc[rr] = fmaf(c * mz, 2.f * wn - w0[rr], acc[rr]);
-      const double dw = (double)wn - (double)w0[rr];
-      s_abs += fabs((double)gv);
-      s_dw += dw * dw;
+      const float dw = wn - w0[rr];
+      f_abs += fabsf(gv);
+      f_dw = fmaf(dw, dw, f_dw);
       const bool bin = INTERIOR || (Y[rr] - dy >= 0 && Y[rr] - dy < g.H && X - dx >= 0 && X - dx < g.W);
       if (bin) {
         const float mm = ms[sl[rr] - dd];
@@ -1343,9 +1358,11 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
         step(d0 + j, b0[j], b2[j]);
         load(d0 + j + P, b0[j], b2[j]);
       }
+      flush();
     }
 #pragma unroll
     for (int j = 0; j < P; ++j) step(SDc - P + j, b0[j], b2[j]);
+    flush();
   } else {
     // software pipeline: the dual values of offsets d+1 and d+2 are in flight while d is used
     float c0[4], c2[4], n0[4], n2[4];
@@ -1363,6 +1380,7 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
       }
       if (d + 2 < SD) load(d + 2, n0, n2);
       step(d, w0, w2);
+      flush();
     }
   }
 #pragma unroll
@@ -1398,6 +1416,13 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
 #pragma unroll
   for (int q = 0; q < 2; ++q) boff[q] = (unsigned)(((size_t)Y[2 * q] * g.W + X[2 * q]) * 2);
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  float f_abs = 0.f, f_dw = 0.f;  // FP32 sums over one ring step (16 terms), then FP64
+  auto flush = [&]() __attribute__((always_inline)) {
+    s_abs += (double)f_abs;
+    s_dw += (double)f_dw;
+    f_abs = 0.f;
+    f_dw = 0.f;
+  };
   auto half = [](unsigned dw, int hi) __attribute__((always_inline)) {
     return (float)__builtin_bit_cast(T, (unsigned short)(hi ? dw >> 16 : dw & 0xffffu));
   };
@@ -1433,9 +1458,9 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
       const float wn = clipf(gv + w0, g.clip);
       bits[rr] = __builtin_bit_cast(unsigned short, (T)wn);
       acc[rr] = fmaf(c * mz, 2.f * wn - w0, acc[rr]);
-      const double dw = (double)wn - (double)w0;
-      s_abs += fabs((double)gv);
-      s_dw += dw * dw;
+      const float dw = wn - w0;
+      f_abs += fabsf(gv);
+      f_dw = fmaf(dw, dw, f_dw);
       const float mm = ms[sl[rr] - dd];
       const float g2 = c * mm * (xs[sl[rr] - dd] - xz);
       const float wn2 = clipf(g2 + w2, g.clip);
@@ -1455,9 +1480,11 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
       step(d0 + j, a0[j], b0[j], b1[j]);
       load(d0 + j + P, a0[j], b0[j], b1[j]);
     }
+    flush();
   }
 #pragma unroll
   for (int j = 0; j < P; ++j) step(SD - P + j, a0[j], b0[j], b1[j]);
+  flush();
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) vs[(size_t)Y[rr] * g.W + X[rr]] = acc[rr];
 }
@@ -2193,10 +2220,11 @@ bool forward_col_setup(Geom& g) {
   t.f_tlx = (g.sx + ncol - 1) / ncol;
   int NY, NX, SY, SX;
   fwd_dims(t, NY, NX, SY, SX);
-  // quad cells when two 8-wave blocks fit a CU's LDS, else the plain tile
+  // quad cells when two 8-wave blocks fit a CU's LDS and there are views for
+  // all eight waves, else the plain 4-wave tile
   Geom q = t;
   q.f_col = 2;
-  if (forward_lds(q) <= 80 * 1024) {
+  if (forward_lds(q) <= 80 * 1024 && g.sk >= 8) {
     g = q;
     return true;
   }
@@ -2272,7 +2300,8 @@ bool adjoint_col_setup(Geom& g) {
   t.a_ntx = (g.W + t.a_tw - 1) / t.a_tw;
   t.a_inv_th = (float)(1.0 / t.a_th);
   t.a_inv_tw = (float)(1.0 / t.a_tw);
-  // view groups: a block's time grows with its views, a launch takes
+  // view groups: a block's time grows with its view passes (its four waves
+  // take views in parallel, so ceil(views / 4) passes), a launch takes
   // ceil(blocks / resident slots) rounds, and every extra group adds a set of
   // partial images to merge; pick the group count with the lowest estimate
   long long per_cu = (long long)((160 * 1024) / lds);
@@ -2281,9 +2310,11 @@ bool adjoint_col_setup(Geom& g) {
   const long long slots = 256 * per_cu, tiles = (long long)t.a_nty * t.a_ntx;
   int best_g = 1;
   double best = 1e30;
+  const double passes1 = (double)((g.sk + 3) / 4);
   for (int G = 1; G <= 8 && G <= g.sk; ++G) {
     const double rounds = (double)((tiles * G + slots - 1) / slots);
-    const double cost = rounds / G + 0.05 * G;
+    const double passes = (double)(((g.sk + G - 1) / G + 3) / 4);
+    const double cost = rounds * passes / passes1 + 0.05 * G;
     if (cost < best - 1e-12) {
       best = cost;
       best_g = G;
