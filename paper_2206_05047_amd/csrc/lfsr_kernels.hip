@@ -141,6 +141,26 @@ __device__ __forceinline__ double* stats_row(const Geom& g, double* stats, const
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
 }
+// The disparity map as a range-checked buffer: a load at a byte offset at or
+// past the map's end (negative offsets included, as unsigned) returns 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t map_rsrc(const float* base, long long n) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)(n * 4), 0x00020000);
+}
+// Disparity of a lane's column, rows 0..N-1 from the map row Yt: clamped to
+// the bound, 0 outside the image.  `ok` false (the lane's column is outside
+// the image or idle) gives every row an offset past the map's end; rows
+// above or below the image have offsets before its start or past its end.
+template <int N>
+__device__ __forceinline__ void load_column(const Geom& g, const float* disp, int Yt, int X, bool ok,
+                                            float (&om)[N]) {
+  const __amdgpu_buffer_rsrc_t rs = map_rsrc(disp, g.p);
+  const int base = ok ? (Yt * g.W + X) * 4 : (int)0x80000000;
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, base + r * g.W * 4, 0, 0));
+    om[r] = __builtin_amdgcn_fmed3f(v, -g.disp_bound, g.disp_bound);
+  }
+}
 template <typename T>
 __device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
   if constexpr (sizeof(T) == 4) {
@@ -561,13 +581,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
   const int px = colok ? lane : 0;
   const int X = Xp0 + px;
   float om[NY];
-#pragma unroll
-  for (int py = 0; py < NY; ++py) {
-    const int Y = Yp0 + py;
-    const bool in = colok && Y >= 0 && Y < g.H && X >= 0 && X < g.W;
-    om[py] = disp[in ? (size_t)Y * g.W + X : 0];
-    om[py] = in ? fminf(fmaxf(om[py], -g.disp_bound), g.disp_bound) : 0.f;
-  }
+  load_column<NY>(g, disp, Yp0, X, colok && X >= 0 && X < g.W, om);
   const int cbase = h * (QUAD ? SX : kColPitch) + px + h;  // tile cell of (row 0, this column)
   // outputs of this lane: lattice point (oi, oj) of the tile, slot s
   const float invT = 1.f / (float)tlx;
@@ -1044,13 +1058,8 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   }
   // disparity of the column (clamped; 0 outside the image)
   float om[TH];
-#pragma unroll
-  for (int r = 0; r < TH; ++r) {
-    const int Y = Y0 + r;
-    const bool in = colin && Y < g.H;
-    om[r] = disp[in ? (size_t)Y * g.W + X : 0];
-    om[r] = in ? fminf(fmaxf(om[r], -g.disp_bound), g.disp_bound) : 0.f;
-  }
+  load_column<TH>(g, disp, Y0, X, colin, om);
+
   float ereg[ESL];
   const int k0 = bz * g.a_vpb;
   const int k1 = min(g.sk, k0 + g.a_vpb);
@@ -1492,7 +1501,7 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
 // T: storage type of x and of the dual; the dual recomputed for the pulled
 // term is the same FP32 value the owning thread stores (rounded) for w_S'.
 template <typename T, int RW>
-__global__ __launch_bounds__(kThreads) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
+__global__ __launch_bounds__(kThreads, RW == 1 ? 1 : 6) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
                                                  T* ws0, T* ws1, float* __restrict__ vs,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
