@@ -141,6 +141,21 @@ __device__ __forceinline__ double* stats_row(const Geom& g, double* stats, const
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000);
 }
+// Largest of the n per-block maxima in pm, this thread's share: four
+// independent loads per trip, so their latencies overlap.
+__device__ __forceinline__ float max_parts(const float* __restrict__ pm, int n) {
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+  int i = threadIdx.x;
+  for (; i + 3 * kThreads < n; i += 4 * kThreads) {
+    m0 = fmaxf(m0, pm[i]);
+    m1 = fmaxf(m1, pm[i + kThreads]);
+    m2 = fmaxf(m2, pm[i + 2 * kThreads]);
+    m3 = fmaxf(m3, pm[i + 3 * kThreads]);
+  }
+  for (; i < n; i += kThreads) m0 = fmaxf(m0, pm[i]);
+  return fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
+}
+
 // The disparity map as a range-checked buffer: a load at a byte offset at or
 // past the map's end (negative offsets included, as unsigned) returns 0.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t map_rsrc(const float* base, long long n) {
@@ -532,7 +547,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
   const int h = g.halo, tlx = g.f_tlx;
   const int NX = (tlx - 1) * ZETA + KB;
   const int SY = NY + 2 * h, SX = NX + 2 * h;  // plain tile: SX <= kColPitch
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int TW4 = QUAD ? 4 * SY * SX : SY * kColPitch;  // floats of the source tile
   float* xs = smem;                                      // plain: [SY][kColPitch], zero outside the image
   const float4* qs = smem_q;                             // quad: [SY][SX] cells
@@ -731,7 +746,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
   const int ETS = (RL + MM) * LX, HVS = RH * LX + MM;
   long long* acc = smem8;                          // [EY][EX] fixed-point accumulator
   float* gs = smem + 2 * EY * EX;                  // [PAD + kb] taps, zeros below
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   float* t2 = gs + PAD + kb + 4 * (ETS + HVS);     // [kb][kb] explicit blur kernel (g.blur2d)
   float* e_ = gs + PAD + kb + wave * (ETS + HVS);  // wave-private LR rows (zero-padded)
   if (g.blur2d)
@@ -742,8 +757,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(Geom g, const TI* __restri
   for (int idx = lane; idx < ETS + HVS; idx += 64) e_[idx] = 0.f;
 
   // fixed-point scale from the producer's block maxima (order-free, so exact)
-  float mloc = 0.f;
-  for (int i = tid; i < npmax; i += kThreads) mloc = fmaxf(mloc, pmax[i]);
+  float mloc = max_parts(pmax, npmax);
   __shared__ float smax[4];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, off, 64));
@@ -993,16 +1007,16 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   constexpr int LX = (TW - 1 + RB) / ZETA + CF + 1;  // staged LR columns
   constexpr int ESL = (RL * LX + 63) / 64;
   constexpr int MM = (2 * RB) / ZETA + 1;            // taps per polyphase phase (at most)
-  extern __shared__ float smem[];
+  extern __shared__ uint4 smem_u4[];  // 16-byte aligned: the accumulator is cleared 16 bytes at a time
+  float* smem = reinterpret_cast<float*>(smem_u4);
   const int h = g.halo, EY = g.a_ey, EX = g.a_ex;  // EY = TH + 2h, EX = TW + 2h <= kColPitch
   unsigned* acc = reinterpret_cast<unsigned*>(smem);  // [EY][kColPitch]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   float* e_ = smem + EY * kColPitch + wave * (RL * LX);  // wave-private LR rows
-  for (int i = tid; i < EY * kColPitch; i += kThreads) acc[i] = 0u;
+  for (int i = tid; i < EY * (kColPitch / 4); i += kThreads) reinterpret_cast<uint4*>(acc)[i] = make_uint4(0u, 0u, 0u, 0u);
 
   // fixed-point scale from the producer's block maxima (order-free, so exact)
-  float mloc = 0.f;
-  for (int i = tid; i < npmax; i += kThreads) mloc = fmaxf(mloc, pmax[i]);
+  float mloc = max_parts(pmax, npmax);
   __shared__ float smax[4];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mloc = fmaxf(mloc, __shfl_xor(mloc, off, 64));
@@ -1020,15 +1034,23 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
 
   const int Y0 = by * TH, X0 = bx * TW;  // tile origin (multiples of ZETA)
   const int i0 = Y0 / ZETA - CF, jb = X0 / ZETA - CF;    // first staged LR row / column
-  // staged LR values of this lane (offset within a view; -1 = zero)
-  int eoff[ESL];
+  // staged LR values of this lane: byte offset within a view, or one past
+  // the view's end (the range-checked view buffer then reads 0)
+  unsigned eoff[ESL];
 #pragma unroll
   for (int s = 0; s < ESL; ++s) {
     const int idx = lane + 64 * s;
     const int a = idx / LX, b = idx - a * LX;
     const int i = i0 + a, j = jb + b;
-    eoff[s] = (idx < RL * LX && i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? i * g.sx + j : -1;
+    eoff[s] = (idx < RL * LX && i >= 0 && i < g.sy && j >= 0 && j < g.sx) ? (unsigned)((i * g.sx + j) * sizeof(TI))
+                                                                            : 0x80000000u;
   }
+  auto fetch = [&](int kv, float (&ev)[ESL]) __attribute__((always_inline)) {
+    const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<TI*>(lr + (size_t)kv * g.q), (short)0, (int)(g.q * sizeof(TI)), 0x00020000);
+#pragma unroll
+    for (int s = 0; s < ESL; ++s) ev[s] = buf_load<TI>(rv, eoff[s]);
+  };
   // this lane's column: own pixel (x < TW) or idle
   const bool own = lane < TW;
   const int x = own ? lane : 0;
@@ -1064,13 +1086,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   const int k0 = bz * g.a_vpb;
   const int k1 = min(g.sk, k0 + g.a_vpb);
   int k = k0 + wave;
-  if (k < k1) {
-#pragma unroll
-    for (int s = 0; s < ESL; ++s) {
-      const float t = (float)lr[(size_t)k * g.q + (eoff[s] >= 0 ? eoff[s] : 0)];
-      ereg[s] = eoff[s] >= 0 ? t : 0.f;
-    }
-  }
+  if (k < k1) fetch(k, ereg);
   __syncthreads();  // accumulator zeroed
 
   unsigned* const accl = acc + (h * kColPitch + x + h);  // accumulator cell of (row 0, this column)
@@ -1078,13 +1094,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
 #pragma unroll
     for (int s = 0; s < ESL; ++s)
       if (lane + 64 * s < RL * LX) e_[lane + 64 * s] = ereg[s];
-    if (k + 4 < k1) {  // prefetch this wave's next view
-#pragma unroll
-      for (int s = 0; s < ESL; ++s) {
-        const float t = (float)lr[(size_t)(k + 4) * g.q + (eoff[s] >= 0 ? eoff[s] : 0)];
-        ereg[s] = eoff[s] >= 0 ? t : 0.f;
-      }
-    }
+    if (k + 4 < k1) fetch(k + 4, ereg);  // prefetch this wave's next view
     __builtin_amdgcn_wave_barrier();
     // B^T D^T, horizontal: one value per staged LR row, scaled by S
     float hrow[RL];
@@ -1146,7 +1156,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcount(Geom g, const float* __re
   extern __shared__ float smem[];
   const int h = g.halo, EY = g.a_ey, EX = g.a_ex;
   unsigned* cnt = reinterpret_cast<unsigned*>(smem);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   for (int i = tid; i < EY * EX; i += kThreads) cnt[i] = 0u;
   const int Y0 = blockIdx.y * TH, X0 = blockIdx.x * TW;
   const bool own = lane < TW;
