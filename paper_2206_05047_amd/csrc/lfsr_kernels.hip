@@ -499,20 +499,30 @@ __device__ __forceinline__ void fwd_walk(const Geom& g, const float* __restrict_
 // The position walk over quad cells: cell (r, c) of the staged tile holds
 // (v, v[c+1] - v, v[r+1] - v, v[r+1][c+1] - v[r+1] - v[c+1] + v), so the
 // bilinear sample at fraction (fy, fx) is v + fx dh + fy (dv + fx dhv): three
-// FMAs after one 16-byte LDS read.
-template <int NY, int TLY, int ZETA, int KB>
+// FMAs after one 16-byte LDS read.  The cell's byte address is one float FMA
+// and one conversion (a cell offset, exact on these small integers) and one
+// shift-add: from the row base of position py held in registers (RB, rowb),
+// else from the tile cell of (row 0, this column) with py added in float.
+template <int NY, int TLY, int ZETA, int KB, bool RB>
 __device__ __forceinline__ void fwd_walk_q(const Geom& g, const float4* __restrict__ qs, const float (&om)[NY],
-                                           int cbase, float sxf, float tau, float rho, float (&acc)[TLY]) {
+                                           const int (&rowb)[RB ? NY : 1], int cb16, float sxf, float tau,
+                                           float rho, float (&acc)[TLY]) {
 #pragma unroll
   for (int i = 0; i < TLY; ++i) acc[i] = 0.f;
-  const float4* qc = qs + cbase;
+  const char* qb = reinterpret_cast<const char*>(qs);
 #pragma unroll
   for (int py = 0; py < NY; ++py) {
     const float sy = tau * om[py], sx = rho * om[py];
     const float fy0 = floorf(sy), fx0 = floorf(sx);
     const float fy = sy - fy0, fx = sx - fx0;
-    const int rel = (int)fmaf(fy0 + (float)py, sxf, fx0);  // exact: small integers
-    const float4 c = qc[rel];
+    float4 c;
+    if constexpr (RB) {
+      const int rel = (int)fmaf(fy0, sxf, fx0);  // cell offset from the row base: exact on these small integers
+      c = *reinterpret_cast<const float4*>(qb + (rel * 16 + rowb[RB ? py : 0]));
+    } else {
+      const int rel = (int)fmaf(fy0 + (float)py, sxf, fx0);  // from (row 0, this column): exact
+      c = *reinterpret_cast<const float4*>(qb + (rel * 16 + cb16));
+    }
     const float val = fmaf(fy, fmaf(fx, c.w, c.z), fmaf(fx, c.y, c.x));
 #pragma unroll
     for (int j = 0; j < (KB + ZETA - 1) / ZETA; ++j) {
@@ -598,6 +608,16 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
   float om[NY];
   load_column<NY>(g, disp, Yp0, X, colok && X >= 0 && X < g.W, om);
   const int cbase = h * (QUAD ? SX : kColPitch) + px + h;  // tile cell of (row 0, this column)
+  // quad walk: byte row bases of the positions, in registers for the CG form
+  // (the wz-step form keeps its registers for the epilogue's loads)
+  constexpr bool RBR = QUAD && !WZD && NY <= 32;
+  const int cb16 = cbase * 16;
+  int rowb[RBR ? NY : 1];
+  rowb[0] = cb16;
+  if constexpr (RBR) {
+#pragma unroll
+    for (int py = 1; py < NY; ++py) rowb[py] = cb16 + py * SX * 16;
+  }
   // outputs of this lane: lattice point (oi, oj) of the tile, slot s
   const float invT = 1.f / (float)tlx;
   int orow[NO], ocol[NO];
@@ -677,7 +697,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
     load_wzd(k, yv, w0);
     const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
     float acc[TLY];
-    if constexpr (QUAD) fwd_walk_q<NY, TLY, ZETA, KB>(g, qs, om, cbase, (float)SX, tau, rho, acc);
+    if constexpr (QUAD) fwd_walk_q<NY, TLY, ZETA, KB, RBR>(g, qs, om, rowb, cb16, (float)SX, tau, rho, acc);
     else fwd_walk<NY, TLY, ZETA, KB>(g, xs, om, cbase, tau, rho, acc);
     finish(acc, k, yv, w0);
   }
