@@ -35,7 +35,8 @@ __device__ __forceinline__ int floordiv(int a, int b) {  // b > 0
   return a >= 0 ? a / b : -((-a + b - 1) / b);
 }
 
-__device__ __forceinline__ float clipf(float u, float c) { return fminf(fmaxf(u, -c), c); }
+// projection onto [-c, c] (c >= 0): the median of (u, -c, c), one v_med3_f32
+__device__ __forceinline__ float clipf(float u, float c) { return __builtin_amdgcn_fmed3f(u, -c, c); }
 
 // floor(v) as an integer in one instruction (v_cvt_flr_i32_f32); with
 // __builtin_amdgcn_fractf (v_fract_f32: v - floor(v), kept below 1) a warp
@@ -1685,9 +1686,9 @@ __device__ __forceinline__ void hp_strip(const Geom& g, const float2* __restrict
         if (dy == 0 && dx == 0) continue;
         const int idx = (dy + RW) * WN + (dx + RW);
         const int d = idx < CTR ? idx : idx - 1;
-        float t = g.cd2[d] * (mz[i] + n[q].y) * (pz[i] - n[q].x);
-        if (!INTERIOR) t = ((rok >> j) & (cok >> q) & 1u) ? t : 0.f;
-        lap[i] += t;
+        float w = g.cd2[d] * (mz[i] + n[q].y);
+        if (!INTERIOR) w = ((rok >> j) & (cok >> q) & 1u) ? w : 0.f;
+        lap[i] = fmaf(w, pz[i] - n[q].x, lap[i]);
       }
     }
   }
