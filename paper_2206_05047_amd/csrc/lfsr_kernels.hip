@@ -1531,6 +1531,9 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
 
 // T: storage type of x and of the dual; the dual recomputed for the pulled
 // term is the same FP32 value the owning thread stores (rounded) for w_S'.
+// Six waves per SIMD (at most 80 VGPRs) for radii 0, 2, 3: six blocks per CU,
+// so a 1152^2 image's 1,296 tiles run in one round instead of five per CU and
+// a tail; the radius-1 kernel keeps its registers (it would spill).
 template <typename T, int RW>
 __global__ __launch_bounds__(kThreads, RW == 1 ? 1 : 6) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
                                                  T* ws0, T* ws1, float* __restrict__ vs,
