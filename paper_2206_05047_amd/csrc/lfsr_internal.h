@@ -10,7 +10,7 @@ constexpr int kMaxTaps = 31;      // blur size limit
 constexpr int kMax2DTaps = 15;    // size limit of an explicit (non-separable) blur kernel
 constexpr int kMaxWin = 15;       // NLTV window limit
 constexpr int kMaxOffsets = kMaxWin * kMaxWin - 1;
-constexpr int kThreads = 256;     // every kernel runs 256-thread (4 x wave64) blocks
+constexpr int kThreads = 256;     // kernels run 256-thread (4 x wave64) blocks, except the NLTV step:
 
 // forward operator: blur positions, horizontal-pass outputs per thread
 constexpr int kFwdSlots = 12;     // NY*NX <= 256*kFwdSlots
@@ -21,7 +21,8 @@ constexpr int kAdjSlots = 5;      // (TH/4)*TW <= 64*kAdjSlots
 constexpr int kAdjVSlots = 4;     // (TH/4)*LX <= 64*kAdjVSlots
 constexpr int kAdjESlots = 3;     // RL*LX <= 64*kAdjESlots
 
-constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles (4 rows per thread)
+constexpr int kTvThreads = 512;   // eight waves on one NLTV tile (2 rows per thread)
+constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles (4 rows per thread in the latter)
 // LDS row pitch (floats) of the column-per-lane kernels' source tile and
 // accumulator: tile width + 2 halo must fit (halo <= 32)
 constexpr int kColPitch = 128;

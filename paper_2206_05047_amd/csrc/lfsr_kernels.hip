@@ -199,17 +199,17 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned off
 // outside [0,H) x [0,W)), into dst[r * ld + c].  Every thread issues a batch
 // of loads (clamped, always in-bounds addresses) before any LDS store, so the
 // global-memory latency is paid once per batch rather than once per element.
-template <typename TS, int BATCH = 8>
+template <typename TS, int BATCH = 8, int NT = kThreads>
 __device__ __forceinline__ void stage_tile(float* __restrict__ dst, int ld, const TS* __restrict__ src, int H, int W,
                                            int Y0, int X0, int rows, int cols) {
   const int n = rows * cols;
   const float inv = 1.f / (float)cols;  // (e + 1/2)/cols in float floors exactly for e < 2^16, cols < 400
-  for (int base = threadIdx.x; base < n; base += kThreads * BATCH) {
+  for (int base = threadIdx.x; base < n; base += NT * BATCH) {
     float v[BATCH];
     int off[BATCH];
 #pragma unroll
     for (int j = 0; j < BATCH; ++j) {
-      const int e = base + j * kThreads;
+      const int e = base + j * NT;
       const int r = (int)(((float)e + 0.5f) * inv), c = e - r * cols;
       const int Y = Y0 + r, X = X0 + c;
       const bool ok = e < n && Y >= 0 && Y < H && X >= 0 && X < W;
@@ -1310,27 +1310,30 @@ __host__ __device__ constexpr int win_dx(int rw, int d) {
 
 // RW > 0: compile-time window radius (offsets and tile pitch become
 // immediates); RW = 0: the radius and offsets come from g at run time.
-template <bool INTERIOR, typename T, int RW>
+template <bool INTERIOR, typename T, int RW, int NT>
 __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__ xs, const float* __restrict__ ms,
                                         const T* wo, T* wn_, float* __restrict__ vs, int X0, int Y0,
                                         double& s_abs, double& s_dw) {
   const int rw = RW > 0 ? RW : g.rw;
   const int LXd = kTvTileX + 2 * rw;
   const int SD = RW > 0 ? (2 * RW + 1) * (2 * RW + 1) - 1 : g.sd;
+  constexpr int NW = NT / 64, RPT = kTvTileY / NW;  // waves; tile rows per thread (ly0 + NW rr)
   const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
   const int X = X0 + lx;
-  int Y[4], sl[4];
-  bool in[4];
+  int Y[RPT], sl[RPT];
+  bool in[RPT];
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int ly = ly0 + 4 * rr;
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int ly = ly0 + NW * rr;
     Y[rr] = Y0 + ly;
     in[rr] = INTERIOR || (Y[rr] < g.H && X < g.W);
     sl[rr] = (ly + rw) * LXd + (lx + rw);
   }
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
-  // statistics: FP32 sums over at most 16 terms (one ring step of four
-  // offsets x four rows, relative error <= 16 u), added to the FP64 totals
+  float acc[RPT];
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) acc[rr] = 0.f;
+  // statistics: FP32 sums over at most 4 RPT terms (one ring step of four
+  // offsets x RPT rows, relative error <= 4 RPT u), added to the FP64 totals
   float f_abs = 0.f, f_dw = 0.f;
   auto flush = [&]() __attribute__((always_inline)) {
     s_abs += (double)f_abs;
@@ -1340,29 +1343,29 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
   };
   // byte offset of pixel (Y[rr], X) within one dual plane (a plane is below
   // 2 GiB), so every dual access is a uniform plane pointer plus this offset
-  unsigned boff[4];
+  unsigned boff[RPT];
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) boff[rr] = in[rr] ? (unsigned)(((size_t)Y[rr] * g.W + X) * sizeof(T)) : 0u;
-  auto load = [&](int d, float (&w0)[4], float (&w2)[4]) __attribute__((always_inline)) {
+  for (int rr = 0; rr < RPT; ++rr) boff[rr] = in[rr] ? (unsigned)(((size_t)Y[rr] * g.W + X) * sizeof(T)) : 0u;
+  auto load = [&](int d, float (&w0)[RPT], float (&w2)[RPT]) __attribute__((always_inline)) {
     const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const T* wd = wo + (size_t)d * g.p;
     const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(wd);
     const __amdgpu_buffer_rsrc_t r2 = plane_rsrc(wd - ((ptrdiff_t)dy * g.W + dx));  // plane shifted by -d
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
+    for (int rr = 0; rr < RPT; ++rr) {
       w0[rr] = in[rr] ? buf_load<T>(r0, boff[rr]) : 0.f;
       const bool bin = INTERIOR || (in[rr] && Y[rr] - dy >= 0 && Y[rr] - dy < g.H && X - dx >= 0 && X - dx < g.W);
       w2[rr] = bin ? buf_load<T>(r2, boff[rr]) : 0.f;
     }
   };
   // offset d with its dual values w0 = w_d(z), w2 = w_d(z - d)
-  auto step = [&](int d, const float (&w0)[4], const float (&w2)[4]) __attribute__((always_inline)) {
+  auto step = [&](int d, const float (&w0)[RPT], const float (&w2)[RPT]) __attribute__((always_inline)) {
     const int dy = RW > 0 ? win_dy(RW, d) : g.ody[d], dx = RW > 0 ? win_dx(RW, d) : g.odx[d];
     const int dd = dy * LXd + dx;
     const float c = g.cd[d];
     const __amdgpu_buffer_rsrc_t rn = plane_rsrc(wn_ + (size_t)d * g.p);
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
+    for (int rr = 0; rr < RPT; ++rr) {
       if (!in[rr]) continue;
       const float xz = xs[sl[rr]], mz = ms[sl[rr]];
       const bool fin = INTERIOR || (Y[rr] + dy >= 0 && Y[rr] + dy < g.H && X + dx >= 0 && X + dx < g.W);
@@ -1388,7 +1391,7 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     // P - 1 offsets of loads stay in flight behind the one being used
     constexpr int P = 4, SDc = (2 * RW + 1) * (2 * RW + 1) - 1;
     static_assert(SDc % P == 0, "the window's offset count is a multiple of 4");
-    float b0[P][4], b2[P][4];
+    float b0[P][RPT], b2[P][RPT];
 #pragma unroll
     for (int j = 0; j < P; ++j) load(j, b0[j], b2[j]);
 #pragma unroll 1
@@ -1405,14 +1408,14 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     flush();
   } else {
     // software pipeline: the dual values of offsets d+1 and d+2 are in flight while d is used
-    float c0[4], c2[4], n0[4], n2[4];
+    float c0[RPT], c2[RPT], n0[RPT], n2[RPT];
     if (SD > 0) load(0, c0, c2);
     if (SD > 1) load(1, n0, n2);
 #pragma unroll 1
     for (int d = 0; d < SD; ++d) {
-      float w0[4], w2[4];
+      float w0[RPT], w2[RPT];
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
+      for (int rr = 0; rr < RPT; ++rr) {
         w0[rr] = c0[rr];
         w2[rr] = c2[rr];
         c0[rr] = n0[rr];
@@ -1424,38 +1427,41 @@ __device__ __forceinline__ void tv_tile(const Geom& g, const float* __restrict__
     }
   }
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr)
+  for (int rr = 0; rr < RPT; ++rr)
     if (in[rr]) vs[(size_t)Y[rr] * g.W + X] = acc[rr];
 }
 
 // Interior tiles with 16-bit duals and an even image width: the same
 // per-pixel arithmetic as tv_tile<true>, with the lanes mapped to pixel pairs
 // so that every dual access is a dword (2-byte accesses cost as much per
-// instruction as 4-byte ones here).  Lane l of wave w owns columns
-// 2 (l & 31) and 2 (l & 31) + 1 of rows 2 w + (l >> 5) and that + 8; slot rr
-// = 2 row-step + column.  Pair (X, X + 1), X even, is one aligned dword of a
+// instruction as 4-byte ones here).  Lane l of wave w (of NW) owns columns
+// 2 (l & 31) and 2 (l & 31) + 1 of rows 2 w + (l >> 5) + 2 NW q for its
+// row-steps q; slot rr = 2 q + column.  Pair (X, X + 1), X even, is one aligned dword of a
 // plane; the pulled term's pair (X - dx, X + 1 - dx) is one aligned dword for
 // even dx and the high / low halves of the two dwords around it for odd dx.
-template <typename T, int RW>
+template <typename T, int RW, int NT>
 __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restrict__ xs, const float* __restrict__ ms,
                                              const T* wo, T* wn_, float* __restrict__ vs, int X0, int Y0,
                                              double& s_abs, double& s_dw) {
   static_assert(sizeof(T) == 2 && RW > 0, "16-bit duals, compile-time radius");
   constexpr int LXd = kTvTileX + 2 * RW, SD = (2 * RW + 1) * (2 * RW + 1) - 1, P = 4;
   static_assert(SD % P == 0, "the window's offset count is a multiple of 4");
+  constexpr int NW = NT / 64, NRS = kTvTileY / (2 * NW), NS = 2 * NRS;  // row-steps, slots per thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int Y[4], X[4], sl[4];
+  int Y[NS], X[NS], sl[NS];
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int lx = 2 * (lane & 31) + (rr & 1), ly = 2 * wave + (lane >> 5) + 8 * (rr >> 1);
+  for (int rr = 0; rr < NS; ++rr) {
+    const int lx = 2 * (lane & 31) + (rr & 1), ly = 2 * wave + (lane >> 5) + 2 * NW * (rr >> 1);
     Y[rr] = Y0 + ly;
     X[rr] = X0 + lx;
     sl[rr] = (ly + RW) * LXd + (lx + RW);
   }
-  unsigned boff[2];  // byte offset of each row's pair (dword aligned)
+  unsigned boff[NRS];  // byte offset of each row's pair (dword aligned)
 #pragma unroll
-  for (int q = 0; q < 2; ++q) boff[q] = (unsigned)(((size_t)Y[2 * q] * g.W + X[2 * q]) * 2);
-  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < NRS; ++q) boff[q] = (unsigned)(((size_t)Y[2 * q] * g.W + X[2 * q]) * 2);
+  float acc[NS];
+#pragma unroll
+  for (int rr = 0; rr < NS; ++rr) acc[rr] = 0.f;
   float f_abs = 0.f, f_dw = 0.f;  // FP32 sums over one ring step (16 terms), then FP64
   auto flush = [&]() __attribute__((always_inline)) {
     s_abs += (double)f_abs;
@@ -1467,28 +1473,28 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
     return (float)__builtin_bit_cast(T, (unsigned short)(hi ? dw >> 16 : dw & 0xffffu));
   };
   // raw dwords of offset d: a0[q] = pair at z, b0[q] / b1[q] = the dword(s) of the pair at z - d
-  auto load = [&](int d, unsigned (&a0)[2], unsigned (&b0)[2], unsigned (&b1)[2]) __attribute__((always_inline)) {
+  auto load = [&](int d, unsigned (&a0)[NRS], unsigned (&b0)[NRS], unsigned (&b1)[NRS]) __attribute__((always_inline)) {
     const int dy = win_dy(RW, d), dx = win_dx(RW, d);
     const T* wd = wo + (size_t)d * g.p;
     const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(wd);
     const __amdgpu_buffer_rsrc_t r2 = plane_rsrc(wd - ((ptrdiff_t)dy * g.W + dx));  // plane shifted by -d
     const unsigned od = (unsigned)(dx & 1) * 2u;  // odd dx: the dwords either side (even: the same one twice)
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NRS; ++q) {
       a0[q] = __builtin_amdgcn_raw_buffer_load_b32(r0, (int)boff[q], 0, 0);
       b0[q] = __builtin_amdgcn_raw_buffer_load_b32(r2, (int)(boff[q] - od), 0, 0);
       b1[q] = __builtin_amdgcn_raw_buffer_load_b32(r2, (int)(boff[q] + od), 0, 0);
     }
   };
-  auto step = [&](int d, const unsigned (&a0)[2], const unsigned (&b0)[2], const unsigned (&b1)[2])
+  auto step = [&](int d, const unsigned (&a0)[NRS], const unsigned (&b0)[NRS], const unsigned (&b1)[NRS])
                   __attribute__((always_inline)) {
     const int dy = win_dy(RW, d), dx = win_dx(RW, d);
     const int dd = dy * LXd + dx;
     const float c = g.cd[d];
     const __amdgpu_buffer_rsrc_t rn = plane_rsrc(wn_ + (size_t)d * g.p);
-    unsigned bits[4];
+    unsigned bits[NS];
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
+    for (int rr = 0; rr < NS; ++rr) {
       const int q = rr >> 1, h = rr & 1;
       const float w0 = half(a0[q], h);
       // odd dx: the pair straddles two dwords (high half of the first, low half of the second)
@@ -1507,10 +1513,10 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
       acc[rr] = fmaf(-(c * mm), 2.f * wn2 - w2, acc[rr]);
     }
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < NRS; ++q)
       __builtin_amdgcn_raw_buffer_store_b32(bits[2 * q] | (bits[2 * q + 1] << 16), rn, (int)boff[q], 0, 0);
   };
-  unsigned a0[P][2], b0[P][2], b1[P][2];
+  unsigned a0[P][NRS], b0[P][NRS], b1[P][NRS];
 #pragma unroll
   for (int j = 0; j < P; ++j) load(j, a0[j], b0[j], b1[j]);
 #pragma unroll 1
@@ -1526,16 +1532,15 @@ __device__ __forceinline__ void tv_tile_pair(const Geom& g, const float* __restr
   for (int j = 0; j < P; ++j) step(SD - P + j, a0[j], b0[j], b1[j]);
   flush();
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) vs[(size_t)Y[rr] * g.W + X[rr]] = acc[rr];
+  for (int rr = 0; rr < NS; ++rr) vs[(size_t)Y[rr] * g.W + X[rr]] = acc[rr];
 }
 
 // T: storage type of x and of the dual; the dual recomputed for the pulled
 // term is the same FP32 value the owning thread stores (rounded) for w_S'.
-// Six waves per SIMD (at most 80 VGPRs) for radii 0, 2, 3: six blocks per CU,
-// so a 1152^2 image's 1,296 tiles run in one round instead of five per CU and
-// a tail; the radius-1 kernel keeps its registers (it would spill).
+// Eight waves share a tile (two rows per thread), so twice as many waves
+// overlap their arithmetic with the dual streams as with four.
 template <typename T, int RW>
-__global__ __launch_bounds__(kThreads, RW == 1 ? 1 : 6) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
+__global__ __launch_bounds__(kTvThreads) void k_tv(Geom g, const T* __restrict__ x, const float* __restrict__ m,
                                                  T* ws0, T* ws1, float* __restrict__ vs,
                                                  double* __restrict__ part, const DevScalars* __restrict__ sc) {
   if (sc->admm_done) return;
@@ -1547,8 +1552,8 @@ __global__ __launch_bounds__(kThreads, RW == 1 ? 1 : 6) void k_tv(Geom g, const 
   float* xs = smem;
   float* ms = xs + LYd * LXd;
   const int X0 = tx * kTvTileX, Y0 = ty * kTvTileY;
-  stage_tile(xs, LXd, x, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
-  stage_tile(ms, LXd, m, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
+  stage_tile<T, 8, kTvThreads>(xs, LXd, x, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
+  stage_tile<float, 8, kTvThreads>(ms, LXd, m, g.H, g.W, Y0 - rw, X0 - rw, LYd, LXd);
   __syncthreads();
   const T* wo = sc->wcur ? ws1 : ws0;
   T* wn_ = sc->wcur ? ws0 : ws1;
@@ -1557,15 +1562,15 @@ __global__ __launch_bounds__(kThreads, RW == 1 ? 1 : 6) void k_tv(Geom g, const 
   if constexpr (sizeof(T) == 2 && RW > 0) {
     // (odd dx reads the dword past the halo's last column: keep that column inside the row)
     if (interior && (g.W & 1) == 0 && X0 + kTvTileX + RW + 1 <= g.W)
-      tv_tile_pair<T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
-    else if (interior) tv_tile<true, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
-    else tv_tile<false, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+      tv_tile_pair<T, RW, kTvThreads>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    else if (interior) tv_tile<true, T, RW, kTvThreads>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    else tv_tile<false, T, RW, kTvThreads>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
   } else {
-    if (interior) tv_tile<true, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
-    else tv_tile<false, T, RW>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    if (interior) tv_tile<true, T, RW, kTvThreads>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
+    else tv_tile<false, T, RW, kTvThreads>(g, xs, ms, wo, wn_, vs, X0, Y0, s_abs, s_dw);
   }
   double v[2] = {s_abs, s_dw};
-  block_sum<2>(v);
+  block_sum<2, kTvThreads / 64>(v);
   if (threadIdx.x == 0) {
     part[(size_t)tt * 2 + 0] = v[0];
     part[(size_t)tt * 2 + 1] = v[1];
@@ -2506,7 +2511,7 @@ void launch_tv(const Geom& g, hipStream_t s, const Bufs& b) {
   by_storage(b.st, [&](auto* tag) {
     using T = LFSR_ELEM(tag);
 #define LFSR_TV(R)                                                                                                 \
-  hipLaunchKernelGGL((k_tv<T, R>), dim3(8 * ((nblocks(tv_grid(g)) + 7) / 8)), dim3(kThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m, \
+  hipLaunchKernelGGL((k_tv<T, R>), dim3(8 * ((nblocks(tv_grid(g)) + 7) / 8)), dim3(kTvThreads), tv_lds(g), s, g, (const T*)b.x, (const float*)b.m, \
                      (T*)b.wS[0], (T*)b.wS[1], b.vs, b.p_tv, (const DevScalars*)b.sc)
     switch (g.rw) {
       case 1: LFSR_TV(1); break;
