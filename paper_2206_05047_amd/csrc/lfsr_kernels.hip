@@ -456,9 +456,9 @@ __global__ __launch_bounds__(kThreads) void k_forward(Geom g, const TS* __restri
 // ---------------------------------------------------------------------------
 // Forward operator, column-per-lane form (same result as k_forward, same
 // fused wz-step epilogue).  A block stages the HR source tile of one LR tile
-// (TLY x f_tlx lattice points) once; each of its four waves then takes whole
-// views (k0 + wave, k0 + wave + 4, ...), so the view loop has no block
-// barrier.  Lane px owns column px of the blur positions (NX <= 64): it walks
+// (TLY x f_tlx lattice points) once; each of its NW waves (eight over quad
+// cells, four over the plain tile) then takes whole views (k0 + wave,
+// k0 + wave + NW, ...), so the view loop has no block barrier.  Lane px owns column px of the blur positions (NX <= 64): it walks
 // the NY positions of its column, warps each one by a bilinear gather from
 // the staged tile and feeds it straight into the vertical blur at the lattice
 // rows, held in registers; the wave then applies the horizontal blur at the
@@ -2353,7 +2353,7 @@ bool adjoint_col_setup(Geom& g) {
   // ceil(blocks / resident slots) rounds, and every extra group adds a set of
   // partial images to merge; pick the group count with the lowest estimate
   long long per_cu = (long long)((160 * 1024) / lds);
-  if (per_cu > 4) per_cu = 4;  // ~110 VGPRs: four waves per SIMD
+  if (per_cu > 4) per_cu = 4;  // ~100 VGPRs: four waves per SIMD
   if (per_cu < 1) per_cu = 1;
   const long long slots = 256 * per_cu, tiles = (long long)t.a_nty * t.a_ntx;
   int best_g = 1;
