@@ -21,7 +21,8 @@ constexpr int kAdjSlots = 5;      // (TH/4)*TW <= 64*kAdjSlots
 constexpr int kAdjVSlots = 4;     // (TH/4)*LX <= 64*kAdjVSlots
 constexpr int kAdjESlots = 3;     // RL*LX <= 64*kAdjESlots
 
-constexpr int kTvThreads = 512;   // eight waves on one NLTV tile (2 rows per thread)
+constexpr int kTvThreads = 512;   // eight waves on one NLTV tile
+constexpr int kCgThreads = 512;   // CG element-wise kernels (2 rows per thread)
 constexpr int kTvTileX = 64, kTvTileY = 16;  // NLTV / normal-operator tiles (4 rows per thread in the latter)
 // LDS row pitch (floats) of the column-per-lane kernels' source tile and
 // accumulator: tile width + 2 halo must fit (halo <= 32)

@@ -84,15 +84,15 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
 
 // Fixed-order sum of component c of nb per-block partials (stride N); every
 // thread of the block receives the same value.
-template <int N>
+template <int N, int NT = kThreads>
 __device__ __forceinline__ void sum_parts(const double* __restrict__ part, int nb, double (&out)[N]) {
 #pragma unroll
   for (int n = 0; n < N; ++n) out[n] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += kThreads) {
+  for (int b = threadIdx.x; b < nb; b += NT) {
 #pragma unroll
     for (int n = 0; n < N; ++n) out[n] += part[(size_t)b * N + n];
   }
-  block_sum<N>(out);
+  block_sum<N, NT / 64>(out);
 }
 
 // Tile of a block in a 1-D grid of 8 * ceil(ntx * nty / 8) blocks.  Blocks
@@ -1769,7 +1769,7 @@ __global__ __launch_bounds__(kThreads, 6) void k_hpstrip(Geom g, const float* __
 // r = -v, p = r, partials of <r, r>.  Block 0 also closes the wz-step's
 // statistics: J(x^(n-1)), the primal residual and the stop test.
 // `r` holds the merged A^T e on entry.
-__global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __restrict__ vs, float* r,
+__global__ __launch_bounds__(kCgThreads) void k_cginit(Geom g, const float* __restrict__ vs, float* r,
                                                      float* __restrict__ pv, double* __restrict__ prr,
                                                      const double* __restrict__ pwzd, int nwzd,
                                                      const double* __restrict__ ptv, int ntv,
@@ -1777,12 +1777,12 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
                                                      const float* __restrict__ adj, int fused) {
   if (sc->admm_done) return;
   double s = 0.0;
-  const long long gstride = (long long)gridDim.x * kThreads * 4;
-  for (long long o0 = blockIdx.x * (long long)kThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
+  const long long gstride = (long long)gridDim.x * kCgThreads * 4;
+  for (long long o0 = blockIdx.x * (long long)kCgThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
     float v[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long o = o0 + j * kThreads;
+      const long long o = o0 + j * kCgThreads;
       v[j] = 0.f;
       if (o < g.p) {
         if (fused) {  // A^T e gathered here from the adjoint's partial images
@@ -1796,7 +1796,7 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long o = o0 + j * kThreads;
+      const long long o = o0 + j * kCgThreads;
       if (o < g.p) {
         const float rv = -v[j];
         r[o] = rv;
@@ -1806,12 +1806,12 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
     }
   }
   double v[1] = {s};
-  block_sum<1>(v);
+  block_sum<1, kCgThreads / 64>(v);
   if (threadIdx.x == 0) prr[blockIdx.x] = v[0];
   if (blockIdx.x != 0) return;
   double a[3], b[2] = {0.0, 0.0};
-  sum_parts<3>(pwzd, nwzd, a);
-  if (g.sd > 0) sum_parts<2>(ptv, ntv, b);
+  sum_parts<3, kCgThreads>(pwzd, nwzd, a);
+  if (g.sd > 0) sum_parts<2, kCgThreads>(ptv, ntv, b);
   if (threadIdx.x == 0) {
     double* row = stats_row(g, stats, sc);
     const double data = (double)g.lambda1 * a[0] + (double)g.lambda2 * a[1];
@@ -1835,7 +1835,7 @@ __global__ __launch_bounds__(kThreads) void k_cginit(Geom g, const float* __rest
 // FP32 estimate: x itself, or the FP32 remainder of a 16-bit x),
 // r -= alpha Hp, partials of the new <r, r>.  CG stops (Algorithm 2) when
 // pi <= tau, pi = 0, or <p, Hp> <= 0.
-__global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ x, float* __restrict__ r,
+__global__ __launch_bounds__(kCgThreads) void k_cgupd(Geom g, float* __restrict__ x, float* __restrict__ r,
                                                     const float* __restrict__ pv, const float* __restrict__ hp,
                                                     const double* __restrict__ prr_prev, double* __restrict__ prr_new,
                                                     const double* __restrict__ pphp, int nphp, int step,
@@ -1844,8 +1844,8 @@ __global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ 
   double t[2];
   {
     double a[1], b[1];
-    sum_parts<1>(prr_prev, g.red_blocks, a);
-    sum_parts<1>(pphp, nphp, b);
+    sum_parts<1, kCgThreads>(prr_prev, g.red_blocks, a);
+    sum_parts<1, kCgThreads>(pphp, nphp, b);
     t[0] = a[0];
     t[1] = b[0];
   }
@@ -1856,12 +1856,12 @@ __global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ 
   }
   const float alpha = (float)(pi / php);
   double s = 0.0;
-  const long long gstride = (long long)gridDim.x * kThreads * 4;
-  for (long long o0 = blockIdx.x * (long long)kThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
+  const long long gstride = (long long)gridDim.x * kCgThreads * 4;
+  for (long long o0 = blockIdx.x * (long long)kCgThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
     float xv[4], pw[4], hw[4], rw[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long o = o0 + j * kThreads;
+      const long long o = o0 + j * kCgThreads;
       const bool in = o < g.p;
       xv[j] = in ? x[o] : 0.f;
       pw[j] = in ? pv[o] : 0.f;
@@ -1870,7 +1870,7 @@ __global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ 
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long o = o0 + j * kThreads;
+      const long long o = o0 + j * kCgThreads;
       if (o < g.p) {
         x[o] = fmaf(alpha, pw[j], xv[j]);
         const float rv = fmaf(-alpha, hw[j], rw[j]);
@@ -1880,34 +1880,34 @@ __global__ __launch_bounds__(kThreads) void k_cgupd(Geom g, float* __restrict__ 
     }
   }
   double v[1] = {s};
-  block_sum<1>(v);
+  block_sum<1, kCgThreads / 64>(v);
   if (threadIdx.x == 0) prr_new[blockIdx.x] = v[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) sc->cg_steps = step;
 }
 
 // CG step part 2: beta = pi_new / pi_old, p = r + beta p.
-__global__ __launch_bounds__(kThreads) void k_cgp(Geom g, const float* __restrict__ r, float* __restrict__ pv,
+__global__ __launch_bounds__(kCgThreads) void k_cgp(Geom g, const float* __restrict__ r, float* __restrict__ pv,
                                                   const double* __restrict__ prr_old,
                                                   const double* __restrict__ prr_new,
                                                   const DevScalars* __restrict__ sc) {
   if (sc->admm_done || sc->cg_done) return;
   double a[1], b[1];
-  sum_parts<1>(prr_new, g.red_blocks, a);
-  sum_parts<1>(prr_old, g.red_blocks, b);
+  sum_parts<1, kCgThreads>(prr_new, g.red_blocks, a);
+  sum_parts<1, kCgThreads>(prr_old, g.red_blocks, b);
   const float beta = (float)(a[0] / b[0]);
-  const long long gstride = (long long)gridDim.x * kThreads * 4;
-  for (long long o0 = blockIdx.x * (long long)kThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
+  const long long gstride = (long long)gridDim.x * kCgThreads * 4;
+  for (long long o0 = blockIdx.x * (long long)kCgThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
     float pw[4], rw[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long o = o0 + j * kThreads;
+      const long long o = o0 + j * kCgThreads;
       const bool in = o < g.p;
       pw[j] = in ? pv[o] : 0.f;
       rw[j] = in ? r[o] : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const long long o = o0 + j * kThreads;
+      const long long o = o0 + j * kCgThreads;
       if (o < g.p) pv[o] = fmaf(beta, pw[j], rw[j]);
     }
   }
@@ -2545,20 +2545,20 @@ void launch_hp(const Geom& g, const float* pv, const float* m, float* out, hipSt
 }
 
 void launch_cginit(const Geom& g, hipStream_t s, const Bufs& b, int fused) {
-  hipLaunchKernelGGL(k_cginit, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.vs, b.r, b.pv,
+  hipLaunchKernelGGL(k_cginit, dim3(g.red_blocks), dim3(kCgThreads), 0, s, g, (const float*)b.vs, b.r, b.pv,
                      b.p_rr[0], (const double*)b.p_wzd, nblocks(forward_grid(g)),
                      (const double*)b.p_tv, nblocks(tv_grid(g)), b.stats, b.sc, (const float*)b.adj, fused);
 }
 
 void launch_cgupd(const Geom& g, int step, hipStream_t s, const Bufs& b) {
   float* xacc = b.st == kStF32 ? (float*)b.x : b.dx;
-  hipLaunchKernelGGL(k_cgupd, dim3(g.red_blocks), dim3(kThreads), 0, s, g, xacc, b.r, (const float*)b.pv,
+  hipLaunchKernelGGL(k_cgupd, dim3(g.red_blocks), dim3(kCgThreads), 0, s, g, xacc, b.r, (const float*)b.pv,
                      (const float*)b.hp, (const double*)b.p_rr[(step - 1) & 1], b.p_rr[step & 1],
                      (const double*)b.p_php, nblocks(tv_grid(g)), step, b.sc);
 }
 
 void launch_cgp(const Geom& g, int step, hipStream_t s, const Bufs& b) {
-  hipLaunchKernelGGL(k_cgp, dim3(g.red_blocks), dim3(kThreads), 0, s, g, (const float*)b.r, b.pv,
+  hipLaunchKernelGGL(k_cgp, dim3(g.red_blocks), dim3(kCgThreads), 0, s, g, (const float*)b.r, b.pv,
                      (const double*)b.p_rr[(step - 1) & 1], (const double*)b.p_rr[step & 1],
                      (const DevScalars*)b.sc);
 }
