@@ -541,7 +541,7 @@ __device__ __forceinline__ void fwd_walk_q(const Geom& g, const float4* __restri
 // without the cap (one shape reaches 134 and keeps three waves per SIMD) and
 // schedule better without it: with it the wz-step spills in its view loop.
 // The 16-bit variants need the cap to stay at 128.
-template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO, bool QUAD>
+template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO, bool QUAD, bool PV>
 __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
                              (QUAD && sizeof(TS) == 4 && sizeof(TO) == 4) ? 2 : 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
                                                      const float* __restrict__ disp, TO* __restrict__ out,
@@ -606,8 +606,10 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
   const bool colok = lane < NX;
   const int px = colok ? lane : 0;
   const int X = Xp0 + px;
+  // PV: one map per view ([k][H][W]), the column reloaded at each view
+  const bool colin = colok && X >= 0 && X < g.W;
   float om[NY];
-  load_column<NY>(g, disp, Yp0, X, colok && X >= 0 && X < g.W, om);
+  if constexpr (!PV) load_column<NY>(g, disp, Yp0, X, colin, om);
   const int cbase = h * (QUAD ? SX : kColPitch) + px + h;  // tile cell of (row 0, this column)
   // quad walk: byte row bases of the positions, in registers for the CG form
   // (the wz-step form keeps its registers for the epilogue's loads)
@@ -693,6 +695,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
     }
   };
   for (int k = k0 + wave; k < k1; k += NW) {
+    if constexpr (PV) load_column<NY>(g, disp + (size_t)k * g.p, Yp0, X, colin, om);
     const int ka = k / g.V, kc = k - ka * g.V;
     float yv[NO], w0[NO];
     load_wzd(k, yv, w0);
@@ -1014,7 +1017,7 @@ static constexpr int adjcol_tw(int zeta) { return zeta * (63 / zeta); }
 static constexpr int adjcol_th(int zeta) { return zeta * (33 / zeta); }
 static constexpr int cdiv_c(int a, int b) { return a >= 0 ? (a + b - 1) / b : -((-a) / b); }
 
-template <int ZETA, int KB, typename TI>
+template <int ZETA, int KB, typename TI, bool PV>
 __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restrict__ lr,
                                                      const float* __restrict__ disp, float* __restrict__ outp,
                                                      const float* __restrict__ pmax, int npmax,
@@ -1099,9 +1102,10 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
       }
     }
   }
-  // disparity of the column (clamped; 0 outside the image)
+  // disparity of the column (clamped; 0 outside the image); PV: one map per
+  // view ([k][H][W]), the column reloaded at each view
   float om[TH];
-  load_column<TH>(g, disp, Y0, X, colin, om);
+  if constexpr (!PV) load_column<TH>(g, disp, Y0, X, colin, om);
 
   float ereg[ESL];
   const int k0 = bz * g.a_vpb;
@@ -1111,6 +1115,10 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
   __syncthreads();  // accumulator zeroed
 
   unsigned* const accl = acc + (h * kColPitch + x + h);  // accumulator cell of (row 0, this column)
+  // PV: the first view's column here, each next one right after the rows of
+  // the current view are done with the registers
+  if constexpr (PV)
+    if (k < k1) load_column<TH>(g, disp + (size_t)k * g.p, Y0, X, colin, om);
   for (; k < k1; k += 4) {
 #pragma unroll
     for (int s = 0; s < ESL; ++s)
@@ -1160,6 +1168,8 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
       atomicAdd(c1, (unsigned)round_i(bl));
       atomicAdd(c1 + 1, (unsigned)round_i(br));
     }
+    if constexpr (PV)
+      if (k + 4 < k1) load_column<TH>(g, disp + (size_t)(k + 4) * g.p, Y0, X, colin, om);
   }
   __syncthreads();
   const size_t tiles = (size_t)g.a_nty * g.a_ntx;
@@ -1171,7 +1181,7 @@ __global__ __launch_bounds__(kThreads) void k_adjcol(Geom g, const TI* __restric
 // Contribution counts of k_adjcol: the same tiles, view groups and targets,
 // each of the four cells of every (view, pixel) counted once; pcnt[block] =
 // the largest count of any cell.  Depends on the disparity map only.
-template <int ZETA, int KB>
+template <int ZETA, int KB, bool PV>
 __global__ __launch_bounds__(kThreads) void k_adjcount(Geom g, const float* __restrict__ disp, int* __restrict__ pcnt) {
   constexpr int TW = adjcol_tw(ZETA), TH = adjcol_th(ZETA);
   extern __shared__ float smem[];
@@ -1183,19 +1193,16 @@ __global__ __launch_bounds__(kThreads) void k_adjcount(Geom g, const float* __re
   const bool own = lane < TW;
   const int x = own ? lane : 0;
   const int X = X0 + x;
+  // the same clamped columns as k_adjcol (PV: one map per view)
+  const bool colin = own && X < g.W;
   float om[TH];
-#pragma unroll
-  for (int r = 0; r < TH; ++r) {
-    const int Y = Y0 + r;
-    const bool in = own && X < g.W && Y < g.H;
-    om[r] = disp[in ? (size_t)Y * g.W + X : 0];
-    om[r] = in ? fminf(fmaxf(om[r], -g.disp_bound), g.disp_bound) : 0.f;
-  }
+  if constexpr (!PV) load_column<TH>(g, disp, Y0, X, colin, om);
   __syncthreads();
   const int k0 = blockIdx.z * g.a_vpb, k1 = min(g.sk, k0 + g.a_vpb);
   const int cb0 = h * EX + x + h;
   if (own) {
     for (int k = k0 + wave; k < k1; k += 4) {
+      if constexpr (PV) load_column<TH>(g, disp + (size_t)k * g.p, Y0, X, colin, om);
       const int ka = k / g.V, kc = k - ka * g.V;
       const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
 #pragma unroll
@@ -2256,9 +2263,10 @@ static constexpr bool fwdcol_shape(int zeta, int kb) {
 static constexpr int fwdcol_tly(int zeta, int kb) { return (void)zeta, (void)kb, 8; }
 
 bool forward_col_setup(Geom& g) {
-  // the column kernels hold one disparity map in registers across all views;
-  // per-view maps take the tiled kernels, which load the map per view
-  if (!fwdcol_shape(g.zeta, g.kb) || g.n_disp > 1 || g.blur2d) return false;
+  // the column kernels hold the lane's disparity column in registers: for
+  // one map across all views, for per-view maps (their PV form) reloaded per
+  // view; explicit 2-D blur kernels take the tiled kernels
+  if (!fwdcol_shape(g.zeta, g.kb) || g.blur2d) return false;
   Geom t = g;
   t.f_col = 1;
   t.f_tly = fwdcol_tly(g.zeta, g.kb);
@@ -2331,7 +2339,7 @@ dim3 adjoint_grid(const Geom& g) { return dim3(g.a_ntx, g.a_nty, g.a_vg); }
 static constexpr bool adjcol_shape(int zeta, int kb) { return fwdcol_shape(zeta, kb); }
 
 bool adjoint_col_setup(Geom& g) {
-  if (!adjcol_shape(g.zeta, g.kb) || g.n_disp > 1 || g.blur2d) return false;
+  if (!adjcol_shape(g.zeta, g.kb) || g.blur2d) return false;
   Geom t = g;
   t.a_col = 1;
   t.a_th = adjcol_th(g.zeta);
@@ -2354,6 +2362,7 @@ bool adjoint_col_setup(Geom& g) {
   // partial images to merge; pick the group count with the lowest estimate
   long long per_cu = (long long)((160 * 1024) / lds);
   if (per_cu > 4) per_cu = 4;  // ~100 VGPRs: four waves per SIMD
+  if (g.n_disp > 1 && per_cu > 3) per_cu = 3;  // per-view maps: ~150 VGPRs, three
   if (per_cu < 1) per_cu = 1;
   const long long slots = 256 * per_cu, tiles = (long long)t.a_nty * t.a_ntx;
   int best_g = 1;
@@ -2394,20 +2403,26 @@ static void launch_fwd_kb(const Geom& g, const TS* src, const float* disp, TO* o
   const dim3 grid = forward_grid(g), blk(kThreads);
   const size_t lds = forward_lds(g);
   if (g.f_col) {
-#define LFSR_FWC(Z, K)                                                                                            \
-  if (g.zeta == Z && g.kb == K) {                                                                                 \
+#define LFSR_FWC_PV(Z, K, PV)                                                                                     \
+  do {                                                                                                            \
     constexpr int TL = fwdcol_tly(Z, K);                                                                          \
     if (g.f_col == 2)                                                                                             \
-      hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, true>), grid, dim3(2 * kThreads), lds, s, g, src, disp, \
-                         out, y, wD, part, pmax, sc, gate);                                                       \
+      hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, true, PV>), grid, dim3(2 * kThreads), lds, s, g, src,   \
+                         disp, out, y, wD, part, pmax, sc, gate);                                                 \
     else                                                                                                          \
-      hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, false>), grid, blk, lds, s, g, src, disp, out, y, wD,   \
-                         part, pmax, sc, gate);                                                                   \
-    return;                                                                                                       \
+      hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, false, PV>), grid, blk, lds, s, g, src, disp, out, y,   \
+                         wD, part, pmax, sc, gate);                                                               \
+  } while (0)
+#define LFSR_FWC(Z, K)                                    \
+  if (g.zeta == Z && g.kb == K) {                         \
+    if (g.n_disp > 1) LFSR_FWC_PV(Z, K, true);            \
+    else LFSR_FWC_PV(Z, K, false);                        \
+    return;                                                \
   }
     LFSR_FWC(2, 3) LFSR_FWC(2, 5) LFSR_FWC(2, 7) LFSR_FWC(2, 9) LFSR_FWC(3, 5) LFSR_FWC(3, 7) LFSR_FWC(3, 9)
     LFSR_FWC(4, 7) LFSR_FWC(4, 9)
 #undef LFSR_FWC
+#undef LFSR_FWC_PV
     return;  // unreachable: forward_col_setup admits only the shapes above
   }
 #define LFSR_FWD(KB) \
@@ -2457,7 +2472,12 @@ void launch_adjoint(const Geom& g, const void* lr, int lr_st, const float* disp,
     if (g.a_col) {
 #define LFSR_ADC(Z, K)                                                                                          \
   if (g.zeta == Z && g.kb == K) {                                                                               \
-    hipLaunchKernelGGL((k_adjcol<Z, K, T>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, b.p_cnt, sc, gate); \
+    if (g.n_disp > 1)                                                                                           \
+      hipLaunchKernelGGL((k_adjcol<Z, K, T, true>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, b.p_cnt,  \
+                         sc, gate);                                                                             \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_adjcol<Z, K, T, false>), grid, blk, lds, s, g, in, disp, b.adj, pm, npmax, b.p_cnt, \
+                         sc, gate);                                                                             \
     return;                                                                                                     \
   }
       LFSR_ADC(2, 3) LFSR_ADC(2, 5) LFSR_ADC(2, 7) LFSR_ADC(2, 9) LFSR_ADC(3, 5) LFSR_ADC(3, 7) LFSR_ADC(3, 9)
@@ -2494,7 +2514,10 @@ void launch_adjcount(const Geom& g, const float* disp, hipStream_t s, const Bufs
   const size_t lds = 4 * (size_t)g.a_ey * g.a_ex;
 #define LFSR_CNT(Z, K)                                                                   \
   if (g.zeta == Z && g.kb == K) {                                                        \
-    hipLaunchKernelGGL((k_adjcount<Z, K>), grid, blk, lds, s, g, disp, b.p_cnt);         \
+    if (g.n_disp > 1)                                                                    \
+      hipLaunchKernelGGL((k_adjcount<Z, K, true>), grid, blk, lds, s, g, disp, b.p_cnt); \
+    else                                                                                 \
+      hipLaunchKernelGGL((k_adjcount<Z, K, false>), grid, blk, lds, s, g, disp, b.p_cnt); \
     return;                                                                              \
   }
   LFSR_CNT(2, 3) LFSR_CNT(2, 5) LFSR_CNT(2, 7) LFSR_CNT(2, 9) LFSR_CNT(3, 5) LFSR_CNT(3, 7) LFSR_CNT(3, 9)
