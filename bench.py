@@ -451,6 +451,33 @@ def main():
                             "steps": reps}
             sv.close()
             log(f"[bench] {name}: {others[name]['ms_per_step']:.2f} ms/solve")
+        # the c3 workload with one disparity map per view (sec 4.1): the scene's
+        # map plus a smooth per-view perturbation of amplitude 0.4, clipped to [-2, 2]
+        c2 = dict(synth.config("c3"), n_disp=81)
+        sc2 = synth.make_scene(c2)
+        H2, W2 = sc2["disp"].shape
+        yy, xx = np.mgrid[0:H2, 0:W2]
+        ph = np.random.default_rng(33).uniform(0, 6, 81)
+        maps = np.stack([np.clip(sc2["disp"] + 0.4 * np.sin(0.21 * yy + 0.13 * xx + ph[k]), -2.0, 2.0)
+                         for k in range(81)]).astype(np.float32)
+        sv = lfsr.Solver(lfsr.make_params(c2, disp_bound=2.0))
+        d2 = torch.from_numpy(maps).cuda()
+        cl = sv.lfsr_forward(torch.from_numpy(sc2["x_gt"].astype(np.float32)).cuda(), d2)
+        y2 = torch.from_numpy(synth.degrade(cl.cpu().numpy(), synth.make_noise(c2))).cuda()
+        o2 = torch.empty((sv.H, sv.W), dtype=torch.float32, device="cuda")
+        sv.lfsr_solve(y2, d2, out=o2, stats=False)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(2):
+            sv.lfsr_solve(y2, d2, out=o2, stats=False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        others["c3_per_view_maps"] = {
+            "workload": synth.WORKLOAD_TEXT["c3"] + "; one disparity map per view (81 maps)",
+            "ms_per_step": (tb - ta) * 1e3 / 2, "value": sv.H * sv.W * sv.sk * c2["n_iter"] * 2 / (tb - ta) / 1e6,
+            "unit": UNIT, "steps": 2}
+        sv.close()
+        log(f"[bench] c3 per-view maps: {others['c3_per_view_maps']['ms_per_step']:.2f} ms/solve")
         line["other_workloads"] = others
 
     if not args.no_cpu_baseline:
