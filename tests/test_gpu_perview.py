@@ -1,9 +1,11 @@
 """GPU parity with one disparity map per view (n_disp = s_k; sec 4.1 gives
 each perspective its own map w_k): the HIP path against the FP64 oracle on
-the same maps.  Cases cover the column-per-lane kernels (c1 shape, the ragged
-3x5-view x3 case, 9x9 views with a wide halo) and the generic kernels (x2 with
-an 11-tap blur).  Tolerances as in test_gpu_parity: operators 2e-5 max-abs
-relative, whole solves 1e-4 relative L2."""
+the same maps.  Cases cover the column-per-lane kernels in their per-view form
+(c1 shape, the ragged 3x5-view x3 case, 9x9 views with a wide halo) and the
+generic kernels (x2 with an 11-tap blur), in FP32 and 16-bit storage.
+Tolerances as in test_gpu_parity and test_gpu_precision: operators 2e-5
+max-abs relative, FP32 solves 1e-4 relative L2, 16-bit solves 2e-3 (FP16) /
+1.5e-2 (BF16)."""
 import numpy as np
 import pytest
 
@@ -97,6 +99,18 @@ def test_per_view_solve_matches_oracle(lfsr, pv):
     print(f"per-view {pv['cfg']['name']}: rel_l2={err:.3e}", flush=True)
     assert err < SOLVE_TOL
     np.testing.assert_allclose(st["hist"][:, 0], sr[:, 0], rtol=1e-4)
+
+
+@pytest.mark.parametrize("st", ["f16", "bf16"])
+def test_per_view_solve_16bit_storage(lfsr, pv, st):
+    """The per-view kernels with 16-bit state storage (same bounds as the
+    single-map 16-bit solves: 2e-3 / 1.5e-2 relative L2)."""
+    s = _solver(lfsr, pv, storage=st)
+    x, _ = s.lfsr_solve(_t(pv["y"]), _t(pv["maps"]))
+    xr, _ = pv["oracle"].solve(pv["y"], pv["maps"])
+    err = synth.rel_l2(_n(x), xr)
+    print(f"per-view {pv['cfg']['name']} {st}: rel_l2={err:.3e}", flush=True)
+    assert err < {"f16": 2e-3, "bf16": 1.5e-2}[st]
 
 
 def test_per_view_occlusion_weight_uses_the_reference_map(lfsr, pv):
