@@ -63,6 +63,7 @@ bool choose_tiles(Geom& g, std::string* err) {
     const long long vpw = (g.sk + nw * groups - 1) / (nw * groups);
     g.f_vpb = (int)(nw * vpw);
   }
+  forward_orbit_setup(g);
 
   // adjoint: prefer >= 1024 tiles; the HR tile must be at least the halo
   const int acand[7][2] = {{16, 8}, {8, 8}, {8, 4}, {4, 8}, {4, 4}, {4, 2}, {4, 1}};

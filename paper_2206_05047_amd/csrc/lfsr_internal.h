@@ -57,9 +57,11 @@ struct Geom {
   int n_iter;                 // rows of the statistics history
   // forward-operator tiling: LR tile and views per block.  f_col selects the
   // column-per-lane kernel: 1 = plain tile, 4 waves; 2 = quad-cell tile, 8
-  // waves (f_vpb = waves x views per wave).
+  // waves (f_vpb = waves x views per wave).  f_orb = 1: the CG-form quad
+  // kernel walks mirror orbits of views instead of single views (same grid)
   int f_tly, f_tlx, f_vpb;
   int f_col;
+  int f_orb;
   // adjoint tiling: LR tile, HR tile, extended (haloed) tile, tile grid
   int a_tly, a_tlx, a_th, a_tw, a_ey, a_ex, a_nty, a_ntx;
   // a_col = 1: column-per-lane adjoint; views split into a_vg groups of a_vpb,
@@ -130,6 +132,9 @@ bool forward_tile_ok(const Geom& g);
 // switch g to the column-per-lane forward kernel when its shape is compiled
 // and its tile fits (sets f_col, f_tly, f_tlx; the caller sets f_vpb)
 bool forward_col_setup(Geom& g);
+// set f_orb when the mirror-orbit walk of the CG-form forward is expected to
+// shorten a block's slowest wave (after f_col and f_vpb are set)
+void forward_orbit_setup(Geom& g);
 bool adjoint_tile_ok(const Geom& g);
 // switch g to the column-per-lane adjoint when its shape is compiled and its
 // tile fits (sets a_col, the tile fields and the view groups)

@@ -534,6 +534,87 @@ __device__ __forceinline__ void fwd_walk_q(const Geom& g, const float4* __restri
   }
 }
 
+// Mirror orbits of an odd angular grid.  With one disparity map, view
+// (tau, rho) samples x at (tau w, rho w) from each position (sec 4.1), so the
+// views (+-tau, +-rho) share |tau| w and |rho| w: for s = a - floor(a) > 0,
+// floor(-a) = -floor(a) - 1 and -a - floor(-a) = 1 - s, and for an integer a
+// the same two values select the cell row below with weight 1, the same
+// sample.  An orbit walk computes the floors and fractions once per position
+// for all its views.  Kinds: four views (tau, rho > 0), two on the centre
+// column (rho = 0), two on the centre row (tau = 0), the centre view.
+enum : int { kOrbQuad = 0, kOrbCol = 1, kOrbRow = 2, kOrbCentre = 3 };
+__host__ __device__ constexpr int orb_nv(int kind) { return kind == kOrbQuad ? 4 : kind == kOrbCentre ? 1 : 2; }
+// member m of an orbit: 1 where its tau (orb_my) or rho (orb_mx) is negated
+__host__ __device__ constexpr int orb_my(int kind, int m) { return kind == kOrbQuad ? m >> 1 : kind == kOrbCol ? m : 0; }
+__host__ __device__ constexpr int orb_mx(int kind, int m) { return kind == kOrbQuad ? m & 1 : kind == kOrbRow ? m : 0; }
+
+// The position walk of one orbit over quad cells (ta = |tau|, ra = |rho|):
+// acc[m] receives the vertical blur of member m's samples, exactly as
+// fwd_walk_q gives it for that view alone.  Cell addresses are taken from
+// (row 0, this column), the row added in float.
+template <int NY, int TLY, int ZETA, int KB, int KIND>
+__device__ __forceinline__ void fwd_walk_orb(const Geom& g, const float4* __restrict__ qs, const float (&om)[NY],
+                                             int cb16, int sx16, float sxf, float ta, float ra,
+                                             float (&acc)[orb_nv(KIND)][TLY]) {
+  constexpr int NV = orb_nv(KIND);
+  constexpr bool HY = KIND == kOrbQuad || KIND == kOrbCol, HX = KIND == kOrbQuad || KIND == kOrbRow;
+#pragma unroll
+  for (int m = 0; m < NV; ++m)
+#pragma unroll
+    for (int i = 0; i < TLY; ++i) acc[m][i] = 0.f;
+  const char* qb = reinterpret_cast<const char*>(qs);
+#pragma unroll
+  for (int py = 0; py < NY; ++py) {
+    // [0]: the positive member, [1]: the mirrored one; fyr = cell row
+    // relative to row 0 of the column, fxc = cell column offset
+    float fy[2] = {0.f, 0.f}, fyr[2] = {(float)py, (float)py}, fx[2] = {0.f, 0.f}, fxc[2] = {0.f, 0.f};
+    if constexpr (HY) {
+      const float s = ta * om[py], f0 = floorf(s), f = s - f0;
+      fy[0] = f;
+      fyr[0] = f0 + (float)py;
+      fy[1] = 1.f - f;
+      fyr[1] = (float)(py - 1) - f0;
+    }
+    if constexpr (HX) {
+      const float s = ra * om[py], f0 = floorf(s), f = s - f0;
+      fx[0] = f;
+      fxc[0] = f0;
+      fx[1] = 1.f - f;
+      fxc[1] = -1.f - f0;
+    }
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+      const int iy = orb_my(KIND, m), ix = orb_mx(KIND, m);
+      // cell offset from (row 0, this column): exact on these small integers
+      const int rel = KIND == kOrbCentre ? 0 : HX ? (int)fmaf(fyr[iy], sxf, fxc[ix]) : (int)(fyr[iy] * sxf);
+      float4 c = *reinterpret_cast<const float4*>(
+          qb + (KIND == kOrbCentre ? cb16 + py * sx16 : rel * 16 + cb16));
+      // whole 16-byte cells also where a kind uses part of one: lanes read
+      // consecutive cells, so the 16-byte form is free of bank conflicts
+      // while one or two words per lane at a 16-byte stride are not
+      if constexpr (!(HY && HX)) asm volatile("" : "+v"(c.x), "+v"(c.y), "+v"(c.z), "+v"(c.w));
+      float val;
+      if constexpr (KIND == kOrbCentre) val = c.x;  // no warp: the cell's own value
+      else if constexpr (HY && HX) val = fmaf(fy[iy], fmaf(fx[ix], c.w, c.z), fmaf(fx[ix], c.y, c.x));
+      else if constexpr (HY) val = fmaf(fy[iy], c.z, c.x);
+      else val = fmaf(fx[ix], c.y, c.x);
+#pragma unroll
+      for (int j = 0; j < (KB + ZETA - 1) / ZETA; ++j) {
+        const int i = py / ZETA - j;
+        const int t = py - i * ZETA;
+        if (i >= 0 && i < TLY && t < KB) acc[m][i] = fmaf(g.g[t], val, acc[m][i]);
+      }
+    }
+  }
+  // keep the accumulation here: the caller reads acc only under a lane
+  // condition, and sinking the FMA chains into that branch would hold every
+  // position's loaded cells live across the walk
+#pragma unroll
+  for (int m = 0; m < NV; ++m)
+#pragma unroll
+    for (int i = 0; i < TLY; ++i) asm volatile("" : "+v"(acc[m][i]));
+}
+
 // QUAD: eight waves per block share a tile of quad cells (fwd_walk_q);
 // otherwise four waves share a plain tile at pitch kColPitch.  The second
 // launch bound is a minimum of waves per SIMD: 4 caps VGPRs at 128 (two
@@ -541,13 +622,17 @@ __device__ __forceinline__ void fwd_walk_q(const Geom& g, const float4* __restri
 // without the cap (one shape reaches 134 and keeps three waves per SIMD) and
 // schedule better without it: with it the wz-step spills in its view loop.
 // The 16-bit variants need the cap to stay at 128.
-template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO, bool QUAD, bool PV>
+// ORB (CG form over quad cells, one disparity map, odd grid): the waves take
+// mirror orbits instead of single views (fwd_walk_orb); the block's range of
+// orbit items is its share of the gridDim.z groups.
+template <bool WZD, int ZETA, int KB, int TLY, typename TS, typename TO, bool QUAD, bool PV, bool ORB = false>
 __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
                              (QUAD && sizeof(TS) == 4 && sizeof(TO) == 4) ? 2 : 4) void k_fwdcol(Geom g, const TS* __restrict__ src,
                                                      const float* __restrict__ disp, TO* __restrict__ out,
                                                      const float* __restrict__ y, TO* __restrict__ wD,
                                                      double* __restrict__ part, float* __restrict__ pmax,
                                                      const DevScalars* __restrict__ sc, int gate) {
+  static_assert(!ORB || (QUAD && !WZD && !PV), "orbit walk: CG form over quad cells with one disparity map");
   if (gated(sc, g, gate)) return;
   constexpr int RB = KB / 2;
   constexpr int NY = (TLY - 1) * ZETA + KB;
@@ -613,7 +698,7 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
   const int cbase = h * (QUAD ? SX : kColPitch) + px + h;  // tile cell of (row 0, this column)
   // quad walk: byte row bases of the positions, in registers for the CG form
   // (the wz-step form keeps its registers for the epilogue's loads)
-  constexpr bool RBR = QUAD && !WZD && NY <= 32;
+  constexpr bool RBR = QUAD && !WZD && !ORB && NY <= 32;
   const int cb16 = cbase * 16;
   int rowb[RBR ? NY : 1];
   rowb[0] = cb16;
@@ -694,16 +779,57 @@ __global__ __launch_bounds__(QUAD ? 2 * kThreads : kThreads,
       }
     }
   };
-  for (int k = k0 + wave; k < k1; k += NW) {
-    if constexpr (PV) load_column<NY>(g, disp + (size_t)k * g.p, Yp0, X, colin, om);
-    const int ka = k / g.V, kc = k - ka * g.V;
-    float yv[NO], w0[NO];
-    load_wzd(k, yv, w0);
-    const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
-    float acc[TLY];
-    if constexpr (QUAD) fwd_walk_q<NY, TLY, ZETA, KB, RBR>(g, qs, om, rowb, cb16, (float)SX, tau, rho, acc);
-    else fwd_walk<NY, TLY, ZETA, KB>(g, xs, om, cbase, tau, rho, acc);
-    finish(acc, k, yv, w0);
+  if constexpr (ORB) {
+    // orbit items: hy hx quads, hy centre-column pairs, hx centre-row pairs,
+    // the centre view; the block takes items [it0, it1) round-robin over its
+    // waves (k0, k1 above are unused)
+    const int ca = (g.U - 1) / 2, cc = (g.V - 1) / 2, nq = ca * cc, nit = nq + ca + cc + 1;
+    const int ipb = (nit + (int)gridDim.z - 1) / (int)gridDim.z;
+    const int it1 = min(nit, bz * ipb + ipb);
+    const float yd[NO] = {}, wd[NO] = {};  // the CG form has no epilogue inputs
+    const int sx16 = SX * 16;
+    const float sxf = (float)SX;
+    int it = bz * ipb + wave;
+    for (; it < it1 && it < nq; it += NW) {
+      const int a = it / cc, ta = 1 + a, ra = 1 + it - a * cc;
+      float acc[4][TLY];
+      fwd_walk_orb<NY, TLY, ZETA, KB, kOrbQuad>(g, qs, om, cb16, sx16, sxf, (float)ta, (float)ra, acc);
+      finish(acc[0], (ca + ta) * g.V + (cc + ra), yd, wd);
+      finish(acc[1], (ca + ta) * g.V + (cc - ra), yd, wd);
+      finish(acc[2], (ca - ta) * g.V + (cc + ra), yd, wd);
+      finish(acc[3], (ca - ta) * g.V + (cc - ra), yd, wd);
+    }
+    for (; it < it1 && it < nq + ca; it += NW) {
+      const int ta = 1 + it - nq;
+      float acc[2][TLY];
+      fwd_walk_orb<NY, TLY, ZETA, KB, kOrbCol>(g, qs, om, cb16, sx16, sxf, (float)ta, 0.f, acc);
+      finish(acc[0], (ca + ta) * g.V + cc, yd, wd);
+      finish(acc[1], (ca - ta) * g.V + cc, yd, wd);
+    }
+    for (; it < it1 && it < nq + ca + cc; it += NW) {
+      const int ra = 1 + it - nq - ca;
+      float acc[2][TLY];
+      fwd_walk_orb<NY, TLY, ZETA, KB, kOrbRow>(g, qs, om, cb16, sx16, sxf, 0.f, (float)ra, acc);
+      finish(acc[0], ca * g.V + (cc + ra), yd, wd);
+      finish(acc[1], ca * g.V + (cc - ra), yd, wd);
+    }
+    if (it < it1) {
+      float acc[1][TLY];
+      fwd_walk_orb<NY, TLY, ZETA, KB, kOrbCentre>(g, qs, om, cb16, sx16, sxf, 0.f, 0.f, acc);
+      finish(acc[0], ca * g.V + cc, yd, wd);
+    }
+  } else {
+    for (int k = k0 + wave; k < k1; k += NW) {
+      if constexpr (PV) load_column<NY>(g, disp + (size_t)k * g.p, Yp0, X, colin, om);
+      const int ka = k / g.V, kc = k - ka * g.V;
+      float yv[NO], w0[NO];
+      load_wzd(k, yv, w0);
+      const float tau = (float)(ka - (g.U - 1) / 2), rho = (float)(kc - (g.V - 1) / 2);
+      float acc[TLY];
+      if constexpr (QUAD) fwd_walk_q<NY, TLY, ZETA, KB, RBR>(g, qs, om, rowb, cb16, (float)SX, tau, rho, acc);
+      else fwd_walk<NY, TLY, ZETA, KB>(g, xs, om, cbase, tau, rho, acc);
+      finish(acc, k, yv, w0);
+    }
   }
   const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   {
@@ -2289,6 +2415,39 @@ bool forward_col_setup(Geom& g) {
   return true;
 }
 
+// Orbit walk for the CG form: estimated VALU instructions per lane of a
+// block's slowest wave, single views against orbits over the same view groups
+// (per blur position: 15 for a view of fwd_walk_q, 47 / 20 / 19 / 5 for an
+// orbit of four / a centre-column pair / a centre-row pair / the centre view
+// in fwd_walk_orb; per view the horizontal pass, TLY + NO (KB + 3)).  Used
+// when the orbits shorten that wave by more than 3 %.
+void forward_orbit_setup(Geom& g) {
+  g.f_orb = 0;
+  if (g.f_col != 2 || g.n_disp != 1 || g.U % 2 == 0 || g.V % 2 == 0 || g.sk < 2) return;
+  const int NW = 8, NY = (g.f_tly - 1) * g.zeta + g.kb;
+  const int NO = (g.f_tly * ((64 - g.kb) / g.zeta + 1) + 63) / 64;
+  const double fin = g.f_tly + NO * (g.kb + 3.0);
+  const double c_view = 15.0 * NY + fin;
+  const int groups = (g.sk + g.f_vpb - 1) / g.f_vpb;
+  const double plain = ((std::min(g.sk, g.f_vpb) + NW - 1) / NW) * c_view;
+  const int ca = (g.U - 1) / 2, cc = (g.V - 1) / 2, nq = ca * cc, nit = nq + ca + cc + 1;
+  auto cost = [&](int it) {
+    if (it < nq) return 47.0 * NY + 4 * fin;
+    if (it < nq + ca) return 20.0 * NY + 2 * fin;
+    if (it < nq + ca + cc) return 19.0 * NY + 2 * fin;
+    return 5.0 * NY + fin;
+  };
+  const int ipb = (nit + groups - 1) / groups;
+  double orb = 0.0;
+  for (int z = 0; z < groups; ++z)
+    for (int w = 0; w < NW; ++w) {
+      double t = 0.0;
+      for (int it = z * ipb + w; it < std::min(nit, z * ipb + ipb); it += NW) t += cost(it);
+      orb = std::max(orb, t);
+    }
+  if (orb < 0.97 * plain) g.f_orb = 1;
+}
+
 bool forward_tile_ok(const Geom& g) {
   int NY, NX, SY, SX;
   fwd_dims(g, NY, NX, SY, SX);
@@ -2406,6 +2565,12 @@ static void launch_fwd_kb(const Geom& g, const TS* src, const float* disp, TO* o
 #define LFSR_FWC_PV(Z, K, PV)                                                                                     \
   do {                                                                                                            \
     constexpr int TL = fwdcol_tly(Z, K);                                                                          \
+    if constexpr (!WZD && !PV)                                                                                    \
+      if (g.f_orb) {                                                                                              \
+        hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, true, false, true>), grid, dim3(2 * kThreads), lds,   \
+                           s, g, src, disp, out, y, wD, part, pmax, sc, gate);                                    \
+        break;                                                                                                    \
+      }                                                                                                           \
     if (g.f_col == 2)                                                                                             \
       hipLaunchKernelGGL((k_fwdcol<WZD, Z, K, TL, TS, TO, true, PV>), grid, dim3(2 * kThreads), lds, s, g, src,   \
                          disp, out, y, wD, part, pmax, sc, gate);                                                 \

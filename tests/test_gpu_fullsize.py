@@ -135,6 +135,20 @@ def test_c3_operators_match_oracle(lfsr):
     assert abs(lhs - rhs) <= 1e-5 * np.sqrt(np.vdot(t_gpu, t_gpu) * np.vdot(e, e))
 
 
+def test_c3_forward_with_integer_warp_offsets(lfsr):
+    """The c3 map rounded to quarter pixels, so that tau * w is an integer at
+    many positions (the mirrored views of the orbit walk then take the cell
+    row or column below with weight 1): forward against the oracle."""
+    c = _case("c3")
+    o = c["o"]
+    d = np.round(c["sc"]["disp"] * 4.0) / 4.0
+    s = lfsr.Solver(lfsr.make_params(c["cfg"], disp_bound=float(np.abs(d).max())))
+    x = np.random.default_rng(37).uniform(0, 1, o.hr_shape).astype(np.float32)
+    err = rel_err(_n(s.lfsr_forward(_t(x), _t(d))), o.forward(x, d))
+    print(f"c3 quarter-pixel map forward: rel_err={err:.3e}", flush=True)
+    assert err < 2e-5
+
+
 def test_c3_occlusion_weight_matches_oracle(lfsr):
     c = _case("c3")
     s = _solver(lfsr, c)
