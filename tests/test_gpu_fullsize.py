@@ -149,6 +149,36 @@ def test_c3_forward_with_integer_warp_offsets(lfsr):
     assert err < 2e-5
 
 
+def test_c3_adjoint_high_dynamic_range_elementwise_bound(lfsr):
+    """The elementwise fixed-point bound of the adjoint (as in test_gpu_parity)
+    at c3, where the adjoint's waves take mirror pairs of views: e of 1e-3
+    with eight outliers of up to 1e3.  Only the bound is asserted: with 81
+    views a cell takes a few hundred terms, each rounded at the scale that
+    max |e| sets, which the max-normalised tolerance of the operator tests
+    (2e-5, for inputs without outliers) does not allow for."""
+    from test_gpu_parity import _transpose_footprint
+    c = _case("c3")
+    o, d, cfg = c["o"], c["sc"]["disp"], c["cfg"]
+    bound_d = float(np.abs(d).max())
+    s = lfsr.Solver(lfsr.make_params(cfg, disp_bound=bound_d))
+    rng = np.random.default_rng(23)
+    e = (1e-3 * rng.standard_normal(o.lr_shape)).astype(np.float32)
+    flat = e.reshape(-1)
+    hot = rng.choice(flat.size, size=8, replace=False)
+    flat[hot] = rng.choice([-1e3, 1e3], size=8) * rng.uniform(0.5, 1.0, size=8)
+    got = _n(s.lfsr_adjoint(_t(e), _t(d)))
+    ref = o.adjoint(e, d)
+    u_abs = np.stack([o.blur_t(o.up(np.abs(e[k]))) for k in range(o.pb.sk)])
+    N, G = _transpose_footprint(cfg, d, bound_d, u_abs)
+    eM = int(np.frexp(np.float32(np.abs(e).max()))[1])
+    hd = int(np.frexp(N.max() + 1.0)[1])
+    bound = N * 2.0 ** (hd + eM - 32) + 128 * 2.0 ** -24 * G
+    err = np.abs(got - ref)
+    print(f"c3 hdr: max err/bound {np.max(err / np.maximum(bound, 1e-30)):.3f}, "
+          f"max-normalised error {rel_err(got, ref):.2e}", flush=True)
+    assert np.all(err <= bound)
+
+
 def test_c3_occlusion_weight_matches_oracle(lfsr):
     c = _case("c3")
     s = _solver(lfsr, c)

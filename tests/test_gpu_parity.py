@@ -84,8 +84,9 @@ def _transpose_footprint(cfg, disp, bound, u_abs):
             for dx in (0, 1):
                 yy, xx = iy + dy, ix + dx
                 ok = (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W)
-                np.add.at(N, (yy[ok], xx[ok]), 1.0)
-                np.add.at(G, (yy[ok], xx[ok]), u_abs[k][ok])
+                idx = (yy[ok] * W + xx[ok]).ravel()
+                N += np.bincount(idx, minlength=H * W).reshape(H, W)
+                G += np.bincount(idx, weights=u_abs[k][ok].ravel(), minlength=H * W).reshape(H, W)
     return N, G
 
 
