@@ -1414,6 +1414,55 @@ __device__ __forceinline__ float adj_merge_near(const Geom& g, const float* __re
   return s;
 }
 
+// The same gather with 32-bit byte offsets through one buffer descriptor over
+// all partial images, the view group's plane in the scalar offset, so the four
+// candidate offsets are computed once for every group (adj_rs_ok: the partial
+// images span less than 2 GiB).
+__device__ __forceinline__ bool adj_rs_ok(const Geom& g) {
+  return (long long)g.a_vg * g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4 < 0x7fffffffLL;
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t adj_rsrc(const Geom& g, const float* adj) {
+  const long long bytes = (long long)g.a_vg * g.a_nty * g.a_ntx * g.a_ey * g.a_ex * 4;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(adj), (short)0,
+                                           (int)(bytes < 0x7fffffffLL ? bytes : 0x7fffffffLL), 0x00020000);
+}
+__device__ __forceinline__ float adj_merge_near_rs(const Geom& g, __amdgpu_buffer_rsrc_t rs, int Y, int X) {
+  const int ty = (int)(((float)Y + 0.5f) * g.a_inv_th), tx = (int)(((float)X + 0.5f) * g.a_inv_tw);
+  const int ly = Y - ty * g.a_th, lx = X - tx * g.a_tw, h = g.halo;
+  const int sy = ly < h ? -1 : (ly >= g.a_th - h ? 1 : 0);
+  const int sx = lx < h ? -1 : (lx >= g.a_tw - h ? 1 : 0);
+  const bool hy = sy != 0 && ty + sy >= 0 && ty + sy < g.a_nty;
+  const bool hx = sx != 0 && tx + sx >= 0 && tx + sx < g.a_ntx;
+  const bool hxy = hx && hy;
+  const int tile = g.a_ey * g.a_ex, grpb = g.a_nty * g.a_ntx * tile * 4;
+  const int r0 = (ly + h) * g.a_ex, r1 = (ly - sy * g.a_th + h) * g.a_ex;
+  const int c0 = lx + h, c1 = lx - sx * g.a_tw + h;
+  const int o00 = ((ty * g.a_ntx + tx) * tile + r0 + c0) * 4;
+  const int o01 = hx ? ((ty * g.a_ntx + tx + sx) * tile + r0 + c1) * 4 : o00;
+  const int o10 = hy ? (((ty + sy) * g.a_ntx + tx) * tile + r1 + c0) * 4 : o00;
+  const int o11 = hxy ? (((ty + sy) * g.a_ntx + tx + sx) * tile + r1 + c1) * 4 : o00;
+  float v[8][4];
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    if (z >= g.a_vg) break;
+    const int so = z * grpb;
+    v[z][0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o00, so, 0));
+    v[z][1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o01, so, 0));
+    v[z][2] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o10, so, 0));
+    v[z][3] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, o11, so, 0));
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int z = 0; z < 8; ++z) {
+    if (z >= g.a_vg) break;
+    s += v[z][0];
+    s += hx ? v[z][1] : 0.f;
+    s += hy ? v[z][2] : 0.f;
+    s += hxy ? v[z][3] : 0.f;
+  }
+  return s;
+}
+
 __global__ __launch_bounds__(kThreads) void k_merge(Geom g, const float* __restrict__ adj, float* __restrict__ out,
                                                     const DevScalars* __restrict__ sc, int gate) {
   if (gated(sc, g, gate)) return;
@@ -1880,13 +1929,15 @@ __global__ __launch_bounds__(kThreads, 6) void k_hpstrip(Geom g, const float* __
   if (interior) hp_strip<true, RW>(g, pm, lx, r0, Y0, X, pz, lap);
   else hp_strip<false, RW>(g, pm, lx, r0, Y0, X, pz, lap);
   double s_dot = 0.0;
+  const bool rs_ok = fused && adj_rs_ok(g);
+  const __amdgpu_buffer_rsrc_t ars = adj_rsrc(g, adj);
 #pragma unroll
   for (int i = 0; i < HS; ++i) {
     const int Y = Y0 + r0 + i;
     if (Y >= g.H || X >= g.W) continue;
     const size_t o = (size_t)Y * g.W + X;
     // fused: A^T A p gathered here from the adjoint's partial images
-    const float ata = fused ? adj_merge_near(g, adj, Y, X) : hp[o];
+    const float ata = rs_ok ? adj_merge_near_rs(g, ars, Y, X) : fused ? adj_merge_near(g, adj, Y, X) : hp[o];
     const float v = g.cA * ata + g.half_theta * lap[i];
     hp[o] = v;
     if (with_dot) s_dot += (double)pz[i] * (double)v;
@@ -1910,6 +1961,8 @@ __global__ __launch_bounds__(kCgThreads) void k_cginit(Geom g, const float* __re
                                                      const float* __restrict__ adj, int fused) {
   if (sc->admm_done) return;
   double s = 0.0;
+  const bool rs_ok = fused && adj_rs_ok(g);
+  const __amdgpu_buffer_rsrc_t ars = adj_rsrc(g, adj);
   const long long gstride = (long long)gridDim.x * kCgThreads * 4;
   for (long long o0 = blockIdx.x * (long long)kCgThreads * 4 + threadIdx.x; o0 < g.p; o0 += gstride) {
     float v[4];
@@ -1920,7 +1973,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cginit(Geom g, const float* __re
       if (o < g.p) {
         if (fused) {  // A^T e gathered here from the adjoint's partial images
           const unsigned Y = (unsigned)o / (unsigned)g.W, X = (unsigned)o - Y * (unsigned)g.W;
-          v[j] = adj_merge_near(g, adj, (int)Y, (int)X);
+          v[j] = rs_ok ? adj_merge_near_rs(g, ars, (int)Y, (int)X) : adj_merge_near(g, adj, (int)Y, (int)X);
         } else {
           v[j] = r[o];
         }
