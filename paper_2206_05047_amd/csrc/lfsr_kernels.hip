@@ -549,9 +549,10 @@ __host__ __device__ constexpr int orb_my(int kind, int m) { return kind == kOrbQ
 __host__ __device__ constexpr int orb_mx(int kind, int m) { return kind == kOrbQuad ? m & 1 : kind == kOrbRow ? m : 0; }
 
 // The position walk of one orbit over quad cells (ta = |tau|, ra = |rho|):
-// acc[m] receives the vertical blur of member m's samples, exactly as
-// fwd_walk_q gives it for that view alone.  Cell addresses are taken from
-// (row 0, this column), the row added in float.
+// acc[m] receives the vertical blur of member m's samples, the samples
+// fwd_walk_q takes for that view alone (a mirrored member's weights 1 - s and
+// its cell sums round differently in the last bit).  Cell addresses are taken
+// from (row 0, this column), the row added in float.
 template <int NY, int TLY, int ZETA, int KB, int KIND>
 __device__ __forceinline__ void fwd_walk_orb(const Geom& g, const float4* __restrict__ qs, const float (&om)[NY],
                                              int cb16, int sx16, float sxf, float ta, float ra,
