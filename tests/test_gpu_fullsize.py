@@ -7,7 +7,10 @@ benchmark times (same parameters, same kernels):
   the stored FP64 oracle solve, relative L2 <= 1e-4, and no 64x64 block of
   it above 1e-3 (a tile, halo or block-order fault is local);
 * c3 single operators and one ADMM iteration against the oracle computed
-  here (the duals and the weight map are local, so every element is checked).
+  here (the duals and the weight map are local, so every element is checked);
+* the mirror-orbit forward on integer warp shifts (c3 map rounded to quarter
+  pixels) and at a second shape (x2, 7x7 blur, ragged 397 x 411 LR views);
+* the adjoint's elementwise fixed-point bound at c3 on a high-dynamic-range e.
 
 The stored values come from tests/golden/make_golden.py (oracle only); the
 inputs are regenerated here and their hashes must match the stored ones.
@@ -147,6 +150,22 @@ def test_c3_forward_with_integer_warp_offsets(lfsr):
     err = rel_err(_n(s.lfsr_forward(_t(x), _t(d))), o.forward(x, d))
     print(f"c3 quarter-pixel map forward: rel_err={err:.3e}", flush=True)
     assert err < 2e-5
+
+
+def test_orbit_forward_x2_ragged(lfsr):
+    """The orbit walk of the CG-form forward at a second kernel shape (x2,
+    7x7 blur) and ragged LR sizes (397 x 411: partial tiles in both
+    directions), 9x9 views over one map in [-2, 2], as is and rounded to
+    quarter pixels, against the oracle."""
+    cfg = dict(synth.config("c3"), name="orbit_x2", sy=397, sx=411, zeta=2, kb=7, sigma_b=1.2, seed=41)
+    o = oracle.Oracle(cfg)
+    d = synth.make_scene(cfg)["disp"]
+    x = np.random.default_rng(43).uniform(0, 1, o.hr_shape).astype(np.float32)
+    for dm in (d, np.round(d * 4.0) / 4.0):
+        s = lfsr.Solver(lfsr.make_params(cfg, disp_bound=float(np.abs(dm).max())))
+        err = rel_err(_n(s.lfsr_forward(_t(x), _t(dm))), o.forward(x, dm))
+        print(f"orbit x2 forward: rel_err={err:.3e}", flush=True)
+        assert err < 2e-5
 
 
 def test_c3_adjoint_high_dynamic_range_elementwise_bound(lfsr):
